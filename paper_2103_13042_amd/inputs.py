@@ -1,0 +1,104 @@
+"""Seeded synthetic inputs for SpAMM: decay matrices in FP32, row-major, N x N.
+
+This module holds no SpAMM arithmetic. It only draws matrices; both the HIP path
+(tests, bench) and the CPU oracle consume exactly the arrays it returns.
+
+Decay classes follow the paper's definitions in its background section (decay
+matrices): exponential decay |A_ij| < c*lambda^|i-j| and algebraic decay
+|A_ij| < c/(|i-j|^lambda + 1).
+
+Random numbers come from one counter-based generator: the SplitMix64 output
+function (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",
+OOPSLA 2014) applied to a counter built from (seed, row, column).  Each element
+is a pure function of (seed, i, j), so the upper-left block of a larger matrix
+equals the smaller matrix, and any row range can be generated on its own.
+Values are computed in float64 and rounded once to float32.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_ROWS_PER_CHUNK = 256
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser on a uint64 array (wrapping arithmetic)."""
+    z = (z ^ (z >> np.uint64(30))) * _M1
+    z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def hash64(seed: int, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """64-bit hash of (seed, i, j); rows/cols broadcast against each other."""
+    ctr = (rows.astype(np.uint64) << np.uint64(32)) | cols.astype(np.uint64)
+    key = np.uint64(((seed + 1) * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF)
+    with np.errstate(over="ignore"):
+        return _mix64(ctr + key)
+
+
+def uniform01(seed: int, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """u in [0, 1) with 53 random bits: (h >> 11) * 2^-53."""
+    h = hash64(seed, rows, cols)
+    return (h >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def sign_pm1(seed: int, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """+1 or -1 from the top bit of the hash."""
+    h = hash64(seed, rows, cols)
+    return 1.0 - 2.0 * (h >> np.uint64(63)).astype(np.float64)
+
+
+def _build(n: int, fn) -> np.ndarray:
+    """Fill an n x n float32 matrix chunk by chunk of rows; fn(rows, cols, dist) -> float64."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    out = np.empty((n, n), dtype=np.float32)
+    cols = np.arange(n, dtype=np.int64)[None, :]
+    for r0 in range(0, n, _ROWS_PER_CHUNK):
+        r1 = min(n, r0 + _ROWS_PER_CHUNK)
+        rows = np.arange(r0, r1, dtype=np.int64)[:, None]
+        dist = np.abs(rows - cols).astype(np.float64)
+        out[r0:r1] = fn(rows, cols, dist).astype(np.float32)
+    return out
+
+
+def exp_decay(n: int, alpha: float, seed: int) -> np.ndarray:
+    """A_ij = exp(-alpha*|i-j|) * (0.5 + 0.5*u_ij), u ~ U[0,1) from `seed`."""
+    return _build(n, lambda r, c, d: np.exp(-alpha * d) * (0.5 + 0.5 * uniform01(seed, r, c)))
+
+
+def algebraic_decay_signed(n: int, seed: int, power: float = 2.0) -> np.ndarray:
+    """A_ij = s_ij / (1 + |i-j|)^power with s_ij = +-1 from `seed`."""
+    return _build(n, lambda r, c, d: sign_pm1(seed, r, c) / (1.0 + d) ** power)
+
+
+def paper_algebraic(n: int) -> np.ndarray:
+    """The paper's synthetic evaluation matrix, a_ij = 0.1 / (|i-j|^0.1 + 1) (section 4.1)."""
+    return _build(n, lambda r, c, d: 0.1 / (d ** 0.1 + 1.0))
+
+
+def uniform_pm1(n: int, seed: int) -> np.ndarray:
+    """Dense test matrix, entries uniform in [-1, 1)."""
+    return _build(n, lambda r, c, d: 2.0 * uniform01(seed, r, c) - 1.0)
+
+
+def uniform_pm1_rect(rows: int, cols: int, seed: int) -> np.ndarray:
+    """Rectangular variant of uniform_pm1 (used to build structured test tiles)."""
+    r = np.arange(rows, dtype=np.int64)[:, None]
+    c = np.arange(cols, dtype=np.int64)[None, :]
+    return (2.0 * uniform01(seed, r, c) - 1.0).astype(np.float32)
+
+
+# Named workloads.  Sizes and parameters mirror the configurations the method is
+# measured on; every matrix is synthetic and seeded.
+def workload_exp1024() -> tuple[np.ndarray, np.ndarray]:
+    """N=1024 exponential decay, alpha=0.05, A seed 0, B seed 1."""
+    return exp_decay(1024, 0.05, 0), exp_decay(1024, 0.05, 1)
+
+
+def workload_alg8192(n: int = 8192) -> tuple[np.ndarray, np.ndarray]:
+    """N=8192 algebraic decay 1/(1+|i-j|)^2 with random signs, A seed 0, B seed 1."""
+    return algebraic_decay_signed(n, 0), algebraic_decay_signed(n, 1)
