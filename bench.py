@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark of the SpAMM hot path on one MI355X.
+
+Default workload: algebraic-decay matrices A_ij = s_ij / (1 + |i-j|)^2 with
+random signs (A seed 0, B seed 1), N = 8192, FP32, leaf tiles of 64, tau = 1e-6.
+
+One step = one pass of the whole hot path over the resident inputs:
+spamm_prepare (leaf norms and pyramids of A and B, plan for tau) followed by
+spamm_execute (cost-balanced schedule and MFMA multiply of the kept pairs).
+HIP events on the stream the library launches on bracket every step and the
+multiply kernel inside it.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+METRIC = "dense-equiv TFLOP/s & speedup vs dense GEMM at rel. Frobenius err ≤1e-4"
+TRAFFIC_FILE = ROOT / "profiles" / "multiply_traffic.json"
+KERNEL_SOURCE = ROOT / "paper_2103_13042_amd" / "csrc" / "kernels.hip"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--tau", type=float, default=1e-6)
+    ap.add_argument("--sweep", default="1e-8,1e-4", help="other tau values timed briefly (empty: none)")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense FP32 GEMM comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget for the oracle's tile sample")
+    return ap.parse_args()
+
+
+def traffic_entry():
+    """HBM bytes per multiply launch from the committed counter summary, if it
+    was taken on the current kernel source (else None)."""
+    try:
+        rec = json.loads(TRAFFIC_FILE.read_text())
+    except (OSError, ValueError):
+        return None
+    sha = hashlib.sha256(KERNEL_SOURCE.read_bytes()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec
+
+
+def main() -> int:
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(
+            f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+            "this SpAMM build measures the single-GPU hot path only",
+            file=sys.stderr,
+        )
+        return 2
+
+    import torch
+
+    from paper_2103_13042_amd import binding as sp
+    from paper_2103_13042_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a visible GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+    torch.backends.cuda.matmul.allow_tf32 = False
+
+    n, leaf, tau = args.n, args.leaf, args.tau
+    bd = sp.bdim(n, leaf)
+    log(f"generating inputs N={n}")
+    t0 = time.perf_counter()
+    a_np, b_np = inputs.workload_alg8192(n)
+    log(f"inputs ready in {time.perf_counter() - t0:.1f}s; uploading")
+    a = torch.from_numpy(a_np).to(dev)
+    b = torch.from_numpy(b_np).to(dev)
+    c = torch.empty_like(a)
+    ws = sp.workspace(n, leaf, dev)
+    bufs = sp.plan_buffers(n, leaf, dev)
+
+    # a device-to-device copy of known size, for scaling HBM byte counters
+    calib = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    calib_dst = torch.empty_like(calib)
+    calib_dst.copy_(calib)
+    torch.cuda.synchronize()
+
+    def step(t):
+        offsets, klist, _ = sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
+        sp.execute(a, b, leaf, offsets, klist, c=c, ws=ws)
+
+    def timed(t, steps, warmup):
+        for _ in range(warmup):
+            step(t)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for e in ev:
+            e[0].record()
+            offsets, klist, _ = sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
+            e[1].record()
+            sp.execute(a, b, leaf, offsets, klist, c=c, ws=ws)
+            e[2].record()
+        end.record()
+        torch.cuda.synchronize()
+        total = start.elapsed_time(end)
+        prep = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        exe = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        pairs = int(bufs[2].item())
+        return total / steps, prep, exe, pairs
+
+    log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
+    ms_step, prep_ms, exec_ms, pairs = timed(tau, args.steps, args.warmup)
+    dense_equiv = 2.0 * n**3 / (ms_step * 1e-3) / 1e12
+    flops_mul = 2.0 * leaf**3 * pairs
+    achieved = flops_mul / (exec_ms * 1e-3) / 1e12
+    log(f"{ms_step:.3f} ms/step (prepare {prep_ms:.3f}, multiply {exec_ms:.3f}), pairs {pairs}, "
+        f"{dense_equiv:.1f} dense-equiv TFLOP/s, multiply {achieved:.1f} TFLOP/s")
+
+    result = {
+        "metric": METRIC,
+        "value": round(dense_equiv, 3),
+        "unit": "TFLOP/s (dense-equivalent 2N^3/t)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"algebraic-decay s_ij/(1+|i-j|)^2, N={n}, leaf {leaf}, tau={tau:g}",
+            "n": n,
+            "leaf": leaf,
+            "tau": tau,
+            "pairs": pairs,
+            "valid_ratio": pairs / bd**3,
+        },
+        "stages_ms": {"prepare": round(prep_ms, 4), "multiply": round(exec_ms, 4)},
+    }
+
+    tr = traffic_entry()
+    result["roofline"] = {
+        "bound": "mfma",
+        "kernel": f"multiply_kernel<{leaf}>",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP32_MFMA_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+        "traffic": tr["hbm_bytes_per_launch"] if tr else None,
+    }
+
+    # approximation + precision against the dense FP32 product
+    if not args.no_dense:
+        for _ in range(2):
+            d = torch.matmul(a, b)
+        torch.cuda.synchronize()
+        reps = 5
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(reps):
+            d = torch.matmul(a, b)
+        s1.record()
+        torch.cuda.synchronize()
+        dense_ms = s0.elapsed_time(s1) / reps
+        rel = float(torch.linalg.norm(c.double() - d.double()) / torch.linalg.norm(d.double()))
+        result["dense_gemm"] = {
+            "library": f"torch.matmul fp32 (torch {torch.__version__}, TF32 off)",
+            "ms": round(dense_ms, 4),
+            "tflops": round(2.0 * n**3 / (dense_ms * 1e-3) / 1e12, 3),
+        }
+        result["speedup_vs_dense"] = round(dense_ms / ms_step, 3)
+        result["rel_err_vs_dense_fp32"] = rel
+        log(f"dense {dense_ms:.3f} ms, speedup {dense_ms / ms_step:.2f}x, rel err vs dense {rel:.2e}")
+        del d
+
+    sweep = {}
+    for tok in [s for s in args.sweep.split(",") if s.strip()]:
+        t = float(tok)
+        ms, pm, em, p = timed(t, max(5, args.steps // 2), 2)
+        sweep[f"{t:g}"] = {
+            "ms_per_step": round(ms, 4),
+            "dense_equiv_tflops": round(2.0 * n**3 / (ms * 1e-3) / 1e12, 3),
+            "multiply_ms": round(em, 4),
+            "mfma_frac": round(2.0 * leaf**3 * p / (em * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+            "pairs": p,
+        }
+        log(f"tau={t:g}: {ms:.3f} ms/step, pairs {p}")
+    if sweep:
+        result["tau_sweep"] = sweep
+        step(tau)  # leave C of the headline tau for the comparison below
+        torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"], result["rel_err_vs_oracle_sampled"] = cpu_baseline(
+            a_np, b_np, c.cpu().numpy(), tau, leaf, args.cpu_seconds
+        )
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def cpu_baseline(a_np, b_np, c_gpu, tau, leaf, budget_s):
+    """Time the FP64 oracle on the host cores: both pyramids in full, then output
+    tiles in a seeded random order until the time budget is spent; the full
+    workload's time is extrapolated from the tile rate.  Also compares the GPU
+    result with the oracle on the tiles it computed."""
+    import oracle
+
+    n = a_np.shape[0]
+    bd = oracle.bdim(n, leaf)
+    log(f"cpu baseline: oracle on {oracle.max_threads()} threads, budget {budget_s:.0f}s")
+    t0 = time.perf_counter()
+    pa, pb = oracle.pyramid(a_np, leaf), oracle.pyramid(b_np, leaf)
+    t_pyr = time.perf_counter() - t0
+    order = np.random.default_rng(1234).permutation(bd * bd)
+    chunk = 256
+    done, t_tiles, num, den = 0, 0.0, 0.0, 0.0
+    while done < bd * bd and t_tiles < budget_s:
+        ids = order[done : done + chunk]
+        tiles = np.stack([ids // bd, ids % bd], axis=1)
+        t1 = time.perf_counter()
+        ct, _, _ = oracle.spamm_tiles(a_np, b_np, tau, leaf, tiles, pyr_a=pa, pyr_b=pb)
+        t_tiles += time.perf_counter() - t1
+        for t, (i, j) in enumerate(tiles):
+            r1, c1 = min(n, (i + 1) * leaf), min(n, (j + 1) * leaf)
+            blk = c_gpu[i * leaf : r1, j * leaf : c1].astype(np.float64)
+            ref = ct[t, : r1 - i * leaf, : c1 - j * leaf]
+            num += float(np.sum((blk - ref) ** 2))
+            den += float(np.sum(ref**2))
+        done += len(ids)
+    full_s = t_pyr + t_tiles * (bd * bd) / done
+    value = 2.0 * n**3 / full_s / 1e12
+    log(f"cpu baseline: pyramids {t_pyr:.1f}s, {done}/{bd * bd} tiles in {t_tiles:.1f}s, est. full {full_s:.1f}s")
+    rel = math.sqrt(num / den) if den > 0 else math.sqrt(num)
+    return (
+        {
+            "value": value,
+            "unit": "TFLOP/s (dense-equivalent 2N^3/t)",
+            "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle: pyramids of A and B in full ({t_pyr:.2f}s) + {done} of {bd * bd} output tiles "
+            f"in seeded random order ({t_tiles:.2f}s), time extrapolated to all tiles ({full_s:.2f}s)",
+        },
+        rel,
+    )
+
+
+if __name__ == "__main__":
+    sys.exit(main())

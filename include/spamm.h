@@ -1,0 +1,147 @@
+/*
+ * spamm.h - C ABI of libspamm.so, Sparse Approximate Matrix Multiplication
+ * (SpAMM) on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Liu et al., "Accelerating Sparse Approximate Matrix
+ * Multiplication on GPUs" (arXiv 2103.13042), section 2.1 and section 3:
+ * C = A*B restricted to the leaf-tile products A[i,k]*B[k,j] whose Frobenius
+ * norm product ||A[i,k]||_F * ||B[k,j]||_F is at least tau (Algorithm 1,
+ * Eq. 1, Eq. 2), with alpha = 1 and beta = 0 (C is overwritten), square N x N.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are FP32, row-major, contiguous, leading dimension N, and live in
+ *    DEVICE memory.  Norms and pyramids are FP64 device arrays.
+ *  - leaf is the edge of a leaf tile (the paper's LoNum); bdim = ceil(N/leaf)
+ *    tiles per side.  The matrix is treated as zero padded to bdim*leaf (and,
+ *    for the quadtree, to leaf*2^Lv with Lv = ceil(log2(bdim))).
+ *  - stream is a hipStream_t (NULL: the default stream).  Every call only
+ *    enqueues work on that stream and returns; nothing synchronises the host.
+ *    Outputs are valid once the stream reaches that point.
+ *  - The library allocates no memory: callers pass every output buffer and a
+ *    workspace of at least spamm_workspace_bytes(N, leaf) bytes.  The library
+ *    never frees or retains caller memory.  Calls that share a workspace must
+ *    be ordered (same stream, or synchronised).
+ *  - Errors: argument checks happen on the host before anything is enqueued;
+ *    on a failure nothing is written and a status code is returned.
+ *    SPAMM_EDEVICE reports a failed HIP call; spamm_last_error() gives the
+ *    detail (per thread).
+ */
+#ifndef SPAMM_H
+#define SPAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spamm_status {
+    SPAMM_OK = 0,
+    SPAMM_EINVAL = 1,       /* invalid argument: size, pointer, tau, aliasing */
+    SPAMM_ENOSPACE = 2,     /* workspace or output capacity too small */
+    SPAMM_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
+    SPAMM_EUNSUPPORTED = 4  /* leaf size or problem size not handled by the GPU path */
+} spamm_status;
+
+/* Largest tile grid the GPU path accepts (bdim <= SPAMM_MAX_BDIM keeps every
+ * pair index of the worst case bdim^3 inside int32). */
+#define SPAMM_MAX_BDIM 1024
+
+/* ceil(n / leaf), or 0 when n <= 0 or leaf <= 0.  Host only. */
+int64_t spamm_bdim(int64_t n, int32_t leaf);
+
+/* Lv = ceil(log2(bdim)): quadtree depth above the leaf tiles (Eq. 1).  Host only. */
+int32_t spamm_levels(int64_t n, int32_t leaf);
+
+/* Number of FP64 entries of a norm pyramid: sum over l = 0..Lv of 4^l.  Host only. */
+int64_t spamm_pyramid_size(int64_t n, int32_t leaf);
+
+/* 1 when the GPU path has kernels for this leaf size (32, 64, 128), else 0. */
+int32_t spamm_leaf_supported(int32_t leaf);
+
+/* Workspace size that every entry point below accepts for (n, leaf); 0 when the
+ * arguments are invalid.  Host only. */
+size_t spamm_workspace_bytes(int64_t n, int32_t leaf);
+
+/* Leaf-tile Frobenius norms (Eq. 2; the get-norm kernel of section 3.2).
+ *   x      [n*n] FP32 device matrix.
+ *   norms  [bdim*bdim] FP64 device output, row-major: norms[i*bdim + j] =
+ *          ||X[i,j]||_F over the tile's elements inside the matrix.
+ * Squares are summed in FP64 (every FP32 square is exact in FP64).  Any leaf
+ * in 1..1024 is accepted.  EINVAL: null pointer, n <= 0, bad leaf. */
+spamm_status spamm_norms(const float* x, int64_t n, int32_t leaf, double* norms, void* stream);
+
+/* Quadtree norm pyramid (Eq. 1 and Eq. 2 at every level, the norms Algorithm 1
+ * tests at each recursion level).
+ *   pyramid [spamm_pyramid_size(n, leaf)] FP64 device output.  Level l (0 = root,
+ *           Lv = leaf tiles) holds 2^l x 2^l node norms, row-major, starting at
+ *           entry (4^l - 1)/3.  Tiles outside the bdim x bdim grid have norm 0.
+ * Each parent's sum of squares is the FP64 sum of its four children's, so a
+ * parent norm is never below a child norm.
+ *   workspace: at least spamm_workspace_bytes(n, leaf) bytes of device memory.
+ * EINVAL as spamm_norms; ENOSPACE when workspace_bytes is too small. */
+spamm_status spamm_pyramid(const float* x, int64_t n, int32_t leaf, double* pyramid, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* Pruning plan (Algorithm 1's norm tests flattened as in section 3.1, and the
+ * bitmap / offset list of the multiplication kernel, Algorithm 2).
+ *   pyr_a, pyr_b  pyramids of A and B from spamm_pyramid (same n, leaf).
+ *   tau           threshold, 0 <= tau <= +inf.  Triple (i,k,j) is kept when
+ *                 the FP64 product pyr_a[leaf](i,k) * pyr_b[leaf](k,j) >= tau;
+ *                 pyramid levels above the leaves only skip ranges of k whose
+ *                 node product is already below tau.
+ *   offsets       [bdim*bdim + 1] int32 device output: the kept k of output
+ *                 tile t = i*bdim + j are klist[offsets[t] .. offsets[t+1]),
+ *                 ascending.  offsets[bdim*bdim] is the total.
+ *   klist         int32 device output, capacity klist_capacity entries, which
+ *                 must be >= bdim^3 (ENOSPACE otherwise).
+ *   pairs         one int64 in device memory: number of kept triples.
+ * EINVAL: null pointer, bad n/leaf, tau NaN or negative. */
+spamm_status spamm_plan(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf, double tau,
+                        int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Multiply the kept leaf pairs of a plan (the multiplication kernel, section 3.3,
+ * with the load balancing of section 3.5.1 done by a cost-balanced static
+ * partition of the output tiles).
+ *   a, b      [n*n] FP32 device inputs; c [n*n] FP32 device output, overwritten
+ *             (beta = 0): tiles with no kept pair become zero.
+ *   offsets, klist: a plan from spamm_plan for the same n and leaf.
+ * Products use FP32 matrix-core instructions with FP32 accumulation, k in
+ * ascending order per output tile.  The leaf must be supported
+ * (spamm_leaf_supported), else EUNSUPPORTED.  EINVAL: null pointer, c
+ * overlapping a or b. */
+spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t leaf, const int32_t* offsets,
+                           const int32_t* klist, float* c, void* workspace, size_t workspace_bytes, void* stream);
+
+/* The first half of the hot path for one product: leaf norms and pyramids of A
+ * and B (one launch each for both matrices) and the plan for tau, as
+ * spamm_pyramid and spamm_plan would produce them.  The pyramids stay in the
+ * workspace; offsets, klist and pairs are as in spamm_plan.  Followed by
+ * spamm_execute this enqueues exactly the kernels of spamm_multiply.
+ * Errors as spamm_plan, plus EINVAL for null a or b. */
+spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau, int32_t leaf, int32_t* offsets,
+                           int32_t* klist, int64_t klist_capacity, int64_t* pairs, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* The whole SpAMM hot path: pyramids of A and B, the plan for tau, and the
+ * multiplication of the kept pairs, enqueued back to back on one stream.
+ *   c      [n*n] FP32 device output, overwritten.
+ *   pairs  one int64 in device memory (may be NULL): number of multiplied
+ *          leaf-tile pairs, i.e. the valid ratio of section 3.5.2 times bdim^3.
+ * Errors as spamm_pyramid, spamm_plan and spamm_execute. */
+spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,
+                            int64_t* pairs, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* spamm_strerror(spamm_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* spamm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPAMM_H */

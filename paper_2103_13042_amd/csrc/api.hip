@@ -1,0 +1,316 @@
+// Host side of libspamm.so: argument checks, workspace layout, and the
+// enqueueing of the kernels of the SpAMM hot path on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "spamm.h"
+#include "internal.h"
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+spamm_status fail(spamm_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+spamm_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SPAMM_OK;
+    return fail(SPAMM_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), int(e));
+}
+
+// Tile geometry of an n x n problem with leaf tiles of edge `leaf`.
+struct Geom {
+    int64_t n = 0, bdim = 0, side = 0, ntiles = 0, pyr = 0;
+    int32_t leaf = 0, lv = 0, nwords = 0;
+};
+
+bool make_geom(int64_t n, int32_t leaf, Geom* g) {
+    if (n <= 0 || leaf <= 0 || leaf > 1024) return false;
+    g->n = n;
+    g->leaf = leaf;
+    g->bdim = (n + leaf - 1) / leaf;
+    int32_t lv = 0;
+    while ((int64_t(1) << lv) < g->bdim) ++lv;
+    g->lv = lv;
+    g->side = int64_t(1) << lv;
+    g->ntiles = g->bdim * g->bdim;
+    g->pyr = spamm::level_offset(lv + 1);
+    g->nwords = int32_t((g->bdim + 63) / 64);
+    return true;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace regions, in order.  Every entry point uses a subset.
+struct Layout {
+    size_t sumsq[2], spyr[2], pyr[2], counts, masks, offsets, klist, pairs, total;
+};
+
+Layout make_layout(const Geom& g) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    for (int m = 0; m < 2; ++m) L.sumsq[m] = take(sizeof(double) * size_t(g.ntiles));
+    for (int m = 0; m < 2; ++m) L.spyr[m] = take(sizeof(double) * size_t(g.pyr));
+    for (int m = 0; m < 2; ++m) L.pyr[m] = take(sizeof(double) * size_t(g.pyr));
+    L.counts = take(sizeof(int32_t) * size_t(g.ntiles));
+    L.masks = take(sizeof(uint64_t) * size_t(g.ntiles) * size_t(g.nwords));
+    L.offsets = take(sizeof(int32_t) * size_t(g.ntiles + 1));
+    L.klist = take(sizeof(int32_t) * size_t(g.ntiles) * size_t(g.bdim));
+    L.pairs = take(sizeof(int64_t));
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+bool overlaps(const void* p, size_t pbytes, const void* q, size_t qbytes) {
+    const char* a = static_cast<const char*>(p);
+    const char* b = static_cast<const char*>(q);
+    return a < b + qbytes && b < a + pbytes;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int device_cus() {
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+spamm_status check_grid(const Geom& g) {
+    if (g.bdim > SPAMM_MAX_BDIM)
+        return fail(SPAMM_EUNSUPPORTED, "tile grid %lld exceeds %d per side", (long long)g.bdim, SPAMM_MAX_BDIM);
+    return SPAMM_OK;
+}
+
+spamm_status check_workspace(const Geom& g, void* ws, size_t bytes) {
+    if (!ws) return fail(SPAMM_EINVAL, "workspace is null");
+    const size_t need = make_layout(g).total;
+    if (bytes < need)
+        return fail(SPAMM_ENOSPACE, "workspace of %zu bytes, %zu needed", bytes, need);
+    return SPAMM_OK;
+}
+
+spamm_status check_tau(double tau) {
+    if (std::isnan(tau) || tau < 0.0) return fail(SPAMM_EINVAL, "tau must be >= 0 (got %g)", tau);
+    return SPAMM_OK;
+}
+
+// Enqueue the norm pass and pyramid for nmat matrices whose pyramids go to pyr_out[m].
+spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
+                              hipStream_t s) {
+    const Layout L = make_layout(g);
+    spamm::NormJob nj{};
+    spamm::PyramidJob pj{};
+    bool vec = (g.n % 4) == 0;
+    for (int m = 0; m < nmat; ++m) {
+        nj.x[m] = x[m];
+        nj.sumsq[m] = at<double>(ws, L.sumsq[m]);
+        nj.norms[m] = nullptr;
+        vec = vec && aligned16(x[m]);
+        pj.sumsq[m] = nj.sumsq[m];
+        pj.spyr[m] = at<double>(ws, L.spyr[m]);
+        pj.pyr[m] = pyr_out[m];
+    }
+    spamm_status st = hip_check(spamm::launch_leaf_norms(nj, nmat, g.n, g.leaf, vec, s), "leaf norm kernel");
+    if (st != SPAMM_OK) return st;
+    return hip_check(spamm::launch_pyramid(pj, nmat, g.bdim, g.lv, s), "pyramid kernel");
+}
+
+spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, double tau, int32_t* offsets,
+                          int32_t* klist, int64_t* pairs, void* ws, hipStream_t s) {
+    const Layout L = make_layout(g);
+    uint64_t* masks = at<uint64_t>(ws, L.masks);
+    int32_t* counts = at<int32_t>(ws, L.counts);
+    spamm_status st =
+        hip_check(spamm::launch_plan_mask(pa, pb, g.bdim, g.lv, tau, masks, counts, s), "plan mask kernel");
+    if (st != SPAMM_OK) return st;
+    st = hip_check(spamm::launch_plan_scan(counts, g.ntiles, offsets, pairs, s), "plan scan kernel");
+    if (st != SPAMM_OK) return st;
+    return hip_check(spamm::launch_plan_fill(masks, offsets, g.ntiles, g.nwords, klist, s), "plan fill kernel");
+}
+
+spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const float* c) {
+    if (!a || !b || !c) return fail(SPAMM_EINVAL, "null matrix pointer");
+    const size_t bytes = sizeof(float) * size_t(g.n) * size_t(g.n);
+    if (overlaps(c, bytes, a, bytes) || overlaps(c, bytes, b, bytes))
+        return fail(SPAMM_EINVAL, "C overlaps A or B");
+    if (!spamm_leaf_supported(g.leaf))
+        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (32, 64, 128)", g.leaf);
+    return SPAMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t spamm_bdim(int64_t n, int32_t leaf) {
+    Geom g;
+    return make_geom(n, leaf, &g) ? g.bdim : 0;
+}
+
+int32_t spamm_levels(int64_t n, int32_t leaf) {
+    Geom g;
+    return make_geom(n, leaf, &g) ? g.lv : 0;
+}
+
+int64_t spamm_pyramid_size(int64_t n, int32_t leaf) {
+    Geom g;
+    return make_geom(n, leaf, &g) ? g.pyr : 0;
+}
+
+int32_t spamm_leaf_supported(int32_t leaf) { return (leaf == 32 || leaf == 64 || leaf == 128) ? 1 : 0; }
+
+size_t spamm_workspace_bytes(int64_t n, int32_t leaf) {
+    Geom g;
+    if (!make_geom(n, leaf, &g) || g.bdim > SPAMM_MAX_BDIM) return 0;
+    return make_layout(g).total;
+}
+
+spamm_status spamm_norms(const float* x, int64_t n, int32_t leaf, double* norms, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!x || !norms) return fail(SPAMM_EINVAL, "null pointer");
+    spamm::NormJob nj{};
+    nj.x[0] = x;
+    nj.sumsq[0] = nullptr;
+    nj.norms[0] = norms;
+    const bool vec = (n % 4) == 0 && aligned16(x);
+    return hip_check(spamm::launch_leaf_norms(nj, 1, n, leaf, vec, static_cast<hipStream_t>(stream)),
+                     "leaf norm kernel");
+}
+
+spamm_status spamm_pyramid(const float* x, int64_t n, int32_t leaf, double* pyramid, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!x || !pyramid) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_grid(g);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    const float* xs[1] = {x};
+    double* ps[1] = {pyramid};
+    return enqueue_pyramids(g, xs, 1, ps, workspace, static_cast<hipStream_t>(stream));
+}
+
+spamm_status spamm_plan(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf, double tau,
+                        int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!pyr_a || !pyr_b || !offsets || !klist || !pairs) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_tau(tau);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_grid(g)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    if (klist_capacity < g.ntiles * g.bdim)
+        return fail(SPAMM_ENOSPACE, "klist capacity %lld < bdim^3 = %lld", (long long)klist_capacity,
+                    (long long)(g.ntiles * g.bdim));
+    return enqueue_plan(g, pyr_a, pyr_b, tau, offsets, klist, pairs, workspace, static_cast<hipStream_t>(stream));
+}
+
+spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t leaf, const int32_t* offsets,
+                           const int32_t* klist, float* c, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_mul_args(g, a, b, c);
+    if (st != SPAMM_OK) return st;
+    if (!offsets || !klist) return fail(SPAMM_EINVAL, "null plan pointer");
+    if ((st = check_grid(g)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    const bool vec = (n % 4) == 0 && aligned16(a) && aligned16(b);
+    return hip_check(spamm::launch_multiply(a, b, c, n, leaf, g.bdim, offsets, klist, vec, device_cus(),
+                                            static_cast<hipStream_t>(stream)),
+                     "multiply kernel");
+}
+
+spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau, int32_t leaf, int32_t* offsets,
+                           int32_t* klist, int64_t klist_capacity, int64_t* pairs, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!a || !b || !offsets || !klist || !pairs) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_tau(tau);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_grid(g)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    if (klist_capacity < g.ntiles * g.bdim)
+        return fail(SPAMM_ENOSPACE, "klist capacity %lld < bdim^3 = %lld", (long long)klist_capacity,
+                    (long long)(g.ntiles * g.bdim));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = make_layout(g);
+    double* pa = at<double>(workspace, L.pyr[0]);
+    double* pb = at<double>(workspace, L.pyr[1]);
+    const float* xs[2] = {a, b};
+    double* ps[2] = {pa, pb};
+    if ((st = enqueue_pyramids(g, xs, 2, ps, workspace, s)) != SPAMM_OK) return st;
+    return enqueue_plan(g, pa, pb, tau, offsets, klist, pairs, workspace, s);
+}
+
+spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,
+                            int64_t* pairs, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_mul_args(g, a, b, c);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_tau(tau)) != SPAMM_OK) return st;
+    if ((st = check_grid(g)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    const Layout L = make_layout(g);
+    int32_t* offsets = at<int32_t>(workspace, L.offsets);
+    int32_t* klist = at<int32_t>(workspace, L.klist);
+    int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
+    st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
+                       stream);
+    if (st != SPAMM_OK) return st;
+    return spamm_execute(a, b, n, leaf, offsets, klist, c, workspace, workspace_bytes, stream);
+}
+
+const char* spamm_strerror(spamm_status status) {
+    switch (status) {
+        case SPAMM_OK: return "success";
+        case SPAMM_EINVAL: return "invalid argument";
+        case SPAMM_ENOSPACE: return "workspace or output capacity too small";
+        case SPAMM_EDEVICE: return "HIP runtime or kernel launch failure";
+        case SPAMM_EUNSUPPORTED: return "unsupported leaf or problem size";
+    }
+    return "unknown status";
+}
+
+const char* spamm_last_error(void) { return g_last_error; }
+
+}  // extern "C"

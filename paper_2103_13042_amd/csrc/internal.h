@@ -1,0 +1,47 @@
+// Internal interface between the host C-ABI (api.hip) and the gfx950 kernels
+// (kernels.hip).  Not installed; the public interface is include/spamm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace spamm {
+
+// Level l of a norm pyramid starts at entry (4^l - 1) / 3 (levels 0..Lv).
+__host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+
+// Up to two matrices are processed by one launch of the norm and pyramid
+// kernels (A and B of one product).
+struct NormJob {
+    const float* x[2];
+    double* sumsq[2];  // [bdim*bdim] leaf sums of squares, or null
+    double* norms[2];  // [bdim*bdim] leaf norms, or null
+};
+
+struct PyramidJob {
+    const double* sumsq[2];  // [bdim*bdim] leaf sums of squares
+    double* spyr[2];         // [pyramid] sums of squares at every level (scratch)
+    double* pyr[2];          // [pyramid] norms at every level (output)
+};
+
+// Norm pass: leaf sums of squares / norms of nmat matrices.
+hipError_t launch_leaf_norms(const NormJob& job, int nmat, int64_t n, int32_t leaf, bool vec, hipStream_t s);
+
+// Pyramid: bottom-up quadtree of sums of squares and norms for nmat matrices.
+hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv, hipStream_t s);
+
+// Plan: per output tile, the ballot bitmap of kept k (words of 64) and its count V.
+hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+                            uint64_t* masks, int32_t* counts, hipStream_t s);
+// Plan: exclusive scan of V into offsets, total into offsets[T] and *pairs.
+hipError_t launch_plan_scan(const int32_t* counts, int64_t ntiles, int32_t* offsets, int64_t* pairs, hipStream_t s);
+// Plan: compaction of the bitmaps into ascending k-lists at the scanned offsets.
+hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* offsets, int64_t ntiles, int nwords,
+                            int32_t* klist, hipStream_t s);
+
+// Multiply: persistent, cost-balanced multiply of the kept pairs into C.
+hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
+                           const int32_t* offsets, const int32_t* klist, bool vec, int num_cus, hipStream_t s);
+
+}  // namespace spamm

@@ -1,0 +1,603 @@
+// gfx950 kernels of the SpAMM hot path.
+//
+//   leaf_sumsq_*      Frobenius norms of every leaf tile (Eq. 2), FP64 sums
+//   pyramid_kernel    quadtree of node norms (Eq. 1), bottom-up, FP64
+//   plan_*            norm-product tests (Algorithm 1 / Algorithm 2's bitmap),
+//                     ballot bitmaps, scan, compaction into ascending k-lists
+//   (in multiply)     cost-balanced static partition of output tiles
+//   multiply_kernel   FP32 MFMA products of the kept leaf pairs into C
+//
+// Wave size is 64 throughout.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace spamm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// --------------------------------------------------------------------------
+// Leaf norms.  A block of 256 threads reads a strip of `leaf` rows by 1024
+// columns; each thread owns 4 adjacent columns and sums their squares down the
+// strip in FP64 (an FP32 square is exact in FP64), then the leaf/4 threads of
+// one tile combine their sums with an xor butterfly.  Rows are read as whole
+// 4 KiB segments per block, so the pass streams HBM at full coalescing.
+
+constexpr int kNormThreads = 256;
+constexpr int kNormCols = kNormThreads * 4;
+
+template <int LEAF, bool VEC>
+__global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, int64_t n, int64_t bdim) {
+    constexpr int G = LEAF / 4;  // threads per tile
+    const int m = blockIdx.z;
+    const float* __restrict__ x = job.x[m];
+    const int64_t col = int64_t(blockIdx.x) * kNormCols + 4 * threadIdx.x;
+    const int64_t r0 = int64_t(blockIdx.y) * LEAF;
+    const int64_t r1 = r0 + LEAF < n ? r0 + LEAF : n;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (VEC) {
+        if (col < n) {
+            const float* p = x + r0 * n + col;
+            int64_t r = r0;
+#pragma unroll 4
+            for (; r + 1 < r1; r += 2) {
+                f4 v = *reinterpret_cast<const f4*>(p);
+                f4 w = *reinterpret_cast<const f4*>(p + n);
+                p += 2 * n;
+                acc0 += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+                acc1 += double(v.z) * double(v.z) + double(v.w) * double(v.w);
+                acc0 += double(w.x) * double(w.x) + double(w.y) * double(w.y);
+                acc1 += double(w.z) * double(w.z) + double(w.w) * double(w.w);
+            }
+            if (r < r1) {
+                f4 v = *reinterpret_cast<const f4*>(p);
+                acc0 += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+                acc1 += double(v.z) * double(v.z) + double(v.w) * double(v.w);
+            }
+        }
+    } else {
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = col + e;
+            if (c >= n) break;
+            double acc = 0.0;
+            for (int64_t r = r0; r < r1; ++r) {
+                const double v = double(x[r * n + c]);
+                acc += v * v;
+            }
+            if (e & 1)
+                acc1 += acc;
+            else
+                acc0 += acc;
+        }
+    }
+    double s = acc0 + acc1;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) s += __shfl_xor(s, off);
+    const int64_t tj = col / LEAF;
+    if ((threadIdx.x % G) == 0 && tj < bdim) {
+        const int64_t t = int64_t(blockIdx.y) * bdim + tj;
+        if (job.sumsq[m]) job.sumsq[m][t] = s;
+        if (job.norms[m]) job.norms[m][t] = sqrt(s);
+    }
+}
+
+// Any other leaf size: one block per tile, strided over its elements.
+__global__ __launch_bounds__(kNormThreads) void leaf_sumsq_generic_kernel(NormJob job, int64_t n, int64_t bdim,
+                                                                          int32_t leaf) {
+    __shared__ double partial[kNormThreads / 64];
+    const int m = blockIdx.z;
+    const float* __restrict__ x = job.x[m];
+    const int64_t ti = blockIdx.y, tj = blockIdx.x;
+    const int64_t rows = (ti * leaf + leaf < n ? leaf : n - ti * leaf);
+    const int64_t cols = (tj * leaf + leaf < n ? leaf : n - tj * leaf);
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < rows * cols; e += kNormThreads) {
+        const int64_t r = ti * leaf + e / cols, c = tj * leaf + e % cols;
+        const double v = double(x[r * n + c]);
+        acc += v * v;
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) partial[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kNormThreads / 64; ++w) s += partial[w];
+        const int64_t t = ti * bdim + tj;
+        if (job.sumsq[m]) job.sumsq[m][t] = s;
+        if (job.norms[m]) job.norms[m][t] = sqrt(s);
+    }
+}
+
+template <int LEAF>
+static hipError_t launch_leaf_fixed(const NormJob& job, int nmat, int64_t n, int64_t bdim, bool vec,
+                                    hipStream_t s) {
+    dim3 grid(unsigned((n + kNormCols - 1) / kNormCols), unsigned(bdim), unsigned(nmat));
+    if (vec)
+        leaf_sumsq_kernel<LEAF, true><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
+    else
+        leaf_sumsq_kernel<LEAF, false><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_norms(const NormJob& job, int nmat, int64_t n, int32_t leaf, bool vec, hipStream_t s) {
+    const int64_t bdim = (n + leaf - 1) / leaf;
+    switch (leaf) {
+        case 16: return launch_leaf_fixed<16>(job, nmat, n, bdim, vec, s);
+        case 32: return launch_leaf_fixed<32>(job, nmat, n, bdim, vec, s);
+        case 64: return launch_leaf_fixed<64>(job, nmat, n, bdim, vec, s);
+        case 128: return launch_leaf_fixed<128>(job, nmat, n, bdim, vec, s);
+        case 256: return launch_leaf_fixed<256>(job, nmat, n, bdim, vec, s);
+        default: break;
+    }
+    dim3 grid{unsigned(bdim), unsigned(bdim), unsigned(nmat)};
+    leaf_sumsq_generic_kernel<<<grid, kNormThreads, 0, s>>>(job, n, bdim, leaf);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Pyramid.  One block per matrix walks the levels bottom-up.  A parent's
+// sum of squares is (s00 + s01) + (s10 + s11) of its children: sums of
+// non-negative FP64 values round monotonically, so a parent is never below any
+// child, and neither is its square root.  That is what lets the plan drop a
+// whole range of k on a parent's test without ever dropping a pair that the
+// leaf test keeps.
+
+constexpr int kPyrThreads = 1024;
+
+__global__ __launch_bounds__(kPyrThreads) void pyramid_kernel(PyramidJob job, int64_t bdim, int lv) {
+    const int m = blockIdx.x;
+    const double* __restrict__ leaf_s = job.sumsq[m];
+    double* __restrict__ sp = job.spyr[m];
+    double* __restrict__ np = job.pyr[m];
+    const int64_t side = int64_t(1) << lv;
+    {
+        const int64_t base = level_offset(lv);
+        for (int64_t idx = threadIdx.x; idx < side * side; idx += kPyrThreads) {
+            const int64_t i = idx >> lv, j = idx & (side - 1);
+            const double v = (i < bdim && j < bdim) ? leaf_s[i * bdim + j] : 0.0;
+            sp[base + idx] = v;
+            np[base + idx] = sqrt(v);
+        }
+    }
+    for (int l = lv - 1; l >= 0; --l) {
+        __syncthreads();
+        const int64_t w = int64_t(1) << l, cw = 2 * w;
+        const int64_t base = level_offset(l), cbase = level_offset(l + 1);
+        for (int64_t idx = threadIdx.x; idx < w * w; idx += kPyrThreads) {
+            const int64_t i = idx >> l, j = idx & (w - 1);
+            const double* c0 = sp + cbase + (2 * i) * cw + 2 * j;
+            const double* c1 = c0 + cw;
+            const double v = (c0[0] + c0[1]) + (c1[0] + c1[1]);
+            sp[base + idx] = v;
+            np[base + idx] = sqrt(v);
+        }
+    }
+}
+
+hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv, hipStream_t s) {
+    pyramid_kernel<<<nmat, kPyrThreads, 0, s>>>(job, bdim, lv);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Plan.  Block (jb, i) owns the 64 output tiles (i, 64*jb .. 64*jb+63) and
+// walks k in chunks of 64.  A chunk is one pyramid node of 64 x 64 leaf tiles
+// (level Lv-6) on each side; when that node product is below tau the chunk is
+// skipped for all 64 tiles at once (uniform branch).  Otherwise the chunk's
+// 64 x 64 block of B leaf norms is staged in LDS, each lane takes one k, and
+// one ballot per tile gives the 64-bit bitmap of kept k.
+
+constexpr int kPlanThreads = 256;
+
+__global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* __restrict__ pyr_a,
+                                                                 const double* __restrict__ pyr_b, int64_t bdim,
+                                                                 int lv, double tau, uint64_t* __restrict__ masks,
+                                                                 int32_t* __restrict__ counts) {
+    __shared__ double sb[64][65];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = blockIdx.y, j0 = int64_t(blockIdx.x) * 64;
+    const int64_t side = int64_t(1) << lv;
+    const int nw = int((bdim + 63) / 64);
+    const double* la = pyr_a + level_offset(lv);
+    const double* lb = pyr_b + level_offset(lv);
+    int cnt[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) cnt[u] = 0;
+    for (int c = 0; c < nw; ++c) {
+        bool keep;
+        if (lv >= 6) {
+            const int lc = lv - 6;
+            const int64_t w = int64_t(1) << lc;
+            keep = pyr_a[level_offset(lc) + (i >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + (j0 >> 6)] >=
+                   tau;
+        } else {
+            keep = pyr_a[0] * pyr_b[0] >= tau;
+        }
+        if (!keep) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int64_t j = j0 + wave + 4 * u;
+                if (lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = 0ull;
+            }
+            continue;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += kPlanThreads) {
+            const int r = e >> 6, cc = e & 63;
+            const int64_t k = int64_t(c) * 64 + r, j = j0 + cc;
+            sb[r][cc] = (k < side && j < side) ? lb[k * side + j] : 0.0;
+        }
+        __syncthreads();
+        const int64_t k = int64_t(c) * 64 + lane;
+        const double a = k < side ? la[i * side + k] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int jj = wave + 4 * u;
+            const int64_t j = j0 + jj;
+            const double p = a * sb[lane][jj];
+            const bool bit = (p >= tau) && (k < bdim) && (j < bdim);
+            const uint64_t mk = __ballot(bit);
+            if (lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = mk;
+            cnt[u] += __popcll(mk);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int64_t j = j0 + wave + 4 * u;
+            if (j < bdim) counts[i * bdim + j] = cnt[u];
+        }
+    }
+}
+
+hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+                            uint64_t* masks, int32_t* counts, hipStream_t s) {
+    dim3 grid(unsigned((bdim + 63) / 64), unsigned(bdim));
+    plan_mask_kernel<<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts);
+    return hipGetLastError();
+}
+
+// Exclusive scan of the per-tile counts: one block of 1024 threads, each
+// thread a contiguous segment, wave scans with shuffles, then across waves.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* __restrict__ counts, int64_t nt,
+                                                                 int32_t* __restrict__ offsets,
+                                                                 int64_t* __restrict__ pairs) {
+    __shared__ int64_t wsum[kScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t seg = (nt + kScanThreads - 1) / kScanThreads;
+    const int64_t b = tid * seg, e = (b + seg < nt ? b + seg : nt);
+    int64_t local = 0;
+    for (int64_t t = b; t < e; ++t) local += counts[t];
+    int64_t incl = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t up = __shfl_up(incl, off);
+        if (lane >= off) incl += up;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += wsum[w];
+    int64_t run = wbase + incl - local;
+    for (int64_t t = b; t < e; ++t) {
+        offsets[t] = int32_t(run);
+        run += counts[t];
+    }
+    if (tid == kScanThreads - 1) {
+        int64_t total = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) total += wsum[w];
+        offsets[nt] = int32_t(total);
+        if (pairs) *pairs = total;
+    }
+}
+
+hipError_t launch_plan_scan(const int32_t* counts, int64_t ntiles, int32_t* offsets, int64_t* pairs, hipStream_t s) {
+    plan_scan_kernel<<<1, kScanThreads, 0, s>>>(counts, ntiles, offsets, pairs);
+    return hipGetLastError();
+}
+
+// Compaction: one wave per output tile; a lane whose bit is set writes its k at
+// the tile's offset plus the number of set bits below it (ascending k).
+__global__ __launch_bounds__(256) void plan_fill_kernel(const uint64_t* __restrict__ masks,
+                                                        const int32_t* __restrict__ offsets, int64_t nt, int nw,
+                                                        int32_t* __restrict__ klist) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= nt) return;
+    int64_t base = offsets[t];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int w = 0; w < nw; ++w) {
+        const uint64_t m = masks[t * nw + w];
+        if ((m >> lane) & 1ull) klist[base + __popcll(m & below)] = w * 64 + lane;
+        base += __popcll(m);
+    }
+}
+
+hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* offsets, int64_t ntiles, int nwords,
+                            int32_t* klist, hipStream_t s) {
+    plan_fill_kernel<<<unsigned((ntiles + 3) / 4), 256, 0, s>>>(masks, offsets, ntiles, nwords, klist);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Multiply.
+//
+// A persistent grid of G workgroups (4 waves each).  Output tiles t = i*bdim+j
+// are split into G contiguous row-major ranges of equal cost, where a tile
+// costs kPairCost per kept pair plus one for writing it; the cost prefix is
+// kPairCost*offsets[t] + t, so each group finds its range by binary search in
+// the plan offsets.  Block ids are remapped so the groups on one XCD (ids
+// congruent mod 8) own neighbouring ranges and share A/B tiles in that XCD's
+// L2.
+//
+// A group runs the flat stream of its (pair, k-chunk) items through a two-stage
+// LDS pipeline: the global loads of item it+1 are in flight while the four
+// waves multiply item it out of LDS.  Wave w computes the (w>>1, w&1) quadrant
+// of the output tile with FP32 MFMA: 32x32x2 for quadrants of 32 or 64, 16x16x4
+// for quadrants of 16.  The sum over a pair's k is re-indexed so that each lane
+// reads 4 consecutive A values with one LDS load: MFMA step s, lane group g
+// uses k = G*s + g, and A is stored in LDS at column (k % G) * (KC/G) + k / G.
+// Tiles are finished in ascending k, then written from the accumulators.
+
+constexpr int kMulThreads = 256;
+constexpr int kPairCost = 4;
+
+template <int LEAF>
+struct MulCfg;
+template <>
+struct MulCfg<32> {
+    static constexpr int MF = 16, KC = 32;
+};
+template <>
+struct MulCfg<64> {
+    static constexpr int MF = 32, KC = 64;
+};
+template <>
+struct MulCfg<128> {
+    static constexpr int MF = 32, KC = 32;
+};
+
+template <int LEAF>
+struct MulGeom {
+    static constexpr int MF = MulCfg<LEAF>::MF;   // MFMA output edge
+    static constexpr int KC = MulCfg<LEAF>::KC;   // k per pipeline stage
+    static constexpr int QM = LEAF / 2;           // quadrant edge per wave
+    static constexpr int NB = QM / MF;            // MFMA blocks per quadrant side
+    static constexpr int G = 64 / MF;             // lane groups along k
+    static constexpr int SPC = KC / G;            // MFMA steps per stage
+    static constexpr int NCH = LEAF / KC;         // stages per leaf pair
+    static constexpr int AST = KC + 4;            // A stage row stride (floats)
+    static constexpr int BST = LEAF + 4;          // B stage row stride (floats)
+    static constexpr int ASZ = LEAF * AST;
+    static constexpr int BSZ = KC * BST;
+    static constexpr int STAGE = ASZ + BSZ;
+    static constexpr int NV = LEAF * KC / 4 / kMulThreads;  // float4 per thread per operand
+    static constexpr int ACC = (MF == 32 ? 16 : 4);         // accumulator floats per MFMA block
+    static_assert(SPC % 4 == 0, "A reads are 4 steps wide");
+    static_assert(NV >= 1 && NV * 4 * kMulThreads == LEAF * KC, "stage split");
+};
+
+template <int MF>
+struct Mfma;
+template <>
+struct Mfma<32> {
+    typedef f16v acc_t;
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    // output element of accumulator register r for lane l: row, col in block
+    static __device__ __forceinline__ int row(int r, int l) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+    static __device__ __forceinline__ int col(int, int l) { return l & 31; }
+};
+template <>
+struct Mfma<16> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r, int l) { return 4 * (l >> 4) + r; }
+    static __device__ __forceinline__ int col(int, int l) { return l & 15; }
+};
+
+// First tile of logical group g: smallest t with (kPairCost*off[t] + t) * G >= g * total.
+__device__ __forceinline__ int64_t partition_start(const int32_t* __restrict__ off, int64_t nt, int64_t g,
+                                                   int64_t groups, int64_t total) {
+    const int64_t target = g * total;
+    int64_t lo = 0, hi = nt;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t(kPairCost) * off[mid] + mid) * groups >= target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int LEAF, bool VEC>
+__global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* __restrict__ A,
+                                                                  const float* __restrict__ B, float* __restrict__ C,
+                                                                  int64_t n, int64_t bdim,
+                                                                  const int32_t* __restrict__ off,
+                                                                  const int32_t* __restrict__ klist) {
+    using Gm = MulGeom<LEAF>;
+    using M = Mfma<Gm::MF>;
+    __shared__ __attribute__((aligned(16))) float lds[2 * Gm::STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ir = lane % Gm::MF, g = lane / Gm::MF;
+
+    // this group's range of output tiles
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t nt = bdim * bdim;
+    const int64_t total = int64_t(kPairCost) * off[nt] + nt;
+    const int64_t t_begin = partition_start(off, nt, lg, groups, total);
+    const int64_t t_end = partition_start(off, nt, lg + 1, groups, total);
+    if (t_begin >= t_end) return;
+    const int64_t q_begin = off[t_begin], q_end = off[t_end];
+    const int64_t nitems = (q_end - q_begin) * Gm::NCH;
+
+    typename M::acc_t acc[Gm::NB][Gm::NB];
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int a = 0; a < Gm::NB; ++a)
+#pragma unroll
+            for (int b = 0; b < Gm::NB; ++b)
+#pragma unroll
+                for (int r = 0; r < Gm::ACC; ++r) acc[a][b][r] = 0.0f;
+    };
+    auto store_tile = [&](int64_t t) {
+        const int64_t ti = t / bdim, tj = t % bdim;
+#pragma unroll
+        for (int a = 0; a < Gm::NB; ++a)
+#pragma unroll
+            for (int b = 0; b < Gm::NB; ++b)
+#pragma unroll
+                for (int r = 0; r < Gm::ACC; ++r) {
+                    const int64_t row = ti * LEAF + wr * Gm::QM + a * Gm::MF + M::row(r, lane);
+                    const int64_t col = tj * LEAF + wc * Gm::QM + b * Gm::MF + M::col(r, lane);
+                    if (row < n && col < n) C[row * n + col] = acc[a][b][r];
+                }
+    };
+
+    // global -> register staging of one (pair, chunk) item
+    f4 ra[Gm::NV], rb[Gm::NV];
+    int64_t pt = t_begin;  // tile of the item being fetched
+    auto fetch = [&](int64_t it) {
+        const int64_t q = q_begin + it / Gm::NCH;
+        const int ch = int(it % Gm::NCH);
+        while (off[pt + 1] <= q) ++pt;
+        const int64_t ti = pt / bdim, tj = pt % bdim, kt = klist[q];
+        const int64_t arow0 = ti * LEAF, acol0 = kt * LEAF + ch * Gm::KC;
+        const int64_t brow0 = kt * LEAF + ch * Gm::KC, bcol0 = tj * LEAF;
+#pragma unroll
+        for (int v = 0; v < Gm::NV; ++v) {
+            const int e = tid + v * kMulThreads;
+            {
+                const int r = e / (Gm::KC / 4), c4 = e % (Gm::KC / 4);
+                const int64_t row = arow0 + r, col = acol0 + 4 * c4;
+                if (VEC) {
+                    ra[v] = (row < n && col < n) ? *reinterpret_cast<const f4*>(A + row * n + col) : f4{0, 0, 0, 0};
+                } else {
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4)
+                        ra[v][q4] = (row < n && col + q4 < n) ? A[row * n + col + q4] : 0.0f;
+                }
+            }
+            {
+                const int r = e / (LEAF / 4), c4 = e % (LEAF / 4);
+                const int64_t row = brow0 + r, col = bcol0 + 4 * c4;
+                if (VEC) {
+                    rb[v] = (row < n && col < n) ? *reinterpret_cast<const f4*>(B + row * n + col) : f4{0, 0, 0, 0};
+                } else {
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4)
+                        rb[v][q4] = (row < n && col + q4 < n) ? B[row * n + col + q4] : 0.0f;
+                }
+            }
+        }
+    };
+    auto commit = [&](int stage) {
+        float* sa = lds + stage * Gm::STAGE;
+        float* sb = sa + Gm::ASZ;
+#pragma unroll
+        for (int v = 0; v < Gm::NV; ++v) {
+            const int e = tid + v * kMulThreads;
+            {
+                const int r = e / (Gm::KC / 4), c4 = e % (Gm::KC / 4);
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int k = 4 * c4 + q4;
+                    sa[r * Gm::AST + (k % Gm::G) * Gm::SPC + k / Gm::G] = ra[v][q4];
+                }
+            }
+            {
+                const int r = e / (LEAF / 4), c4 = e % (LEAF / 4);
+                *reinterpret_cast<f4*>(sb + r * Gm::BST + 4 * c4) = rb[v];
+            }
+        }
+    };
+    auto compute = [&](int stage) {
+        const float* sa = lds + stage * Gm::STAGE;
+        const float* sb = sa + Gm::ASZ;
+#pragma unroll
+        for (int q = 0; q < Gm::SPC / 4; ++q) {
+            f4 av[Gm::NB];
+#pragma unroll
+            for (int a = 0; a < Gm::NB; ++a)
+                av[a] = *reinterpret_cast<const f4*>(sa + (wr * Gm::QM + a * Gm::MF + ir) * Gm::AST + g * Gm::SPC +
+                                                     4 * q);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int s = 4 * q + u;
+                float bv[Gm::NB];
+#pragma unroll
+                for (int b = 0; b < Gm::NB; ++b) bv[b] = sb[(Gm::G * s + g) * Gm::BST + wc * Gm::QM + b * Gm::MF + ir];
+#pragma unroll
+                for (int a = 0; a < Gm::NB; ++a)
+#pragma unroll
+                    for (int b = 0; b < Gm::NB; ++b) acc[a][b] = M::step(av[a][u], bv[b], acc[a][b]);
+            }
+        }
+    };
+
+    zero_acc();
+    int64_t t = t_begin;
+    if (nitems > 0) {
+        fetch(0);
+        commit(0);
+    }
+    for (int64_t it = 0; it < nitems; ++it) {
+        if (it % Gm::NCH == 0) {
+            const int64_t q = q_begin + it / Gm::NCH;
+            while (off[t + 1] <= q) {  // tile t is complete (or has no pairs)
+                store_tile(t);
+                zero_acc();
+                ++t;
+            }
+        }
+        const bool more = it + 1 < nitems;
+        if (more) fetch(it + 1);
+        __syncthreads();
+        compute(int(it & 1));
+        if (more) commit(int((it + 1) & 1));
+    }
+    while (t < t_end) {
+        store_tile(t);
+        zero_acc();
+        ++t;
+    }
+}
+
+template <int LEAF>
+static hipError_t launch_mul(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                             const int32_t* offsets, const int32_t* klist, bool vec, int num_cus, hipStream_t s) {
+    const int64_t nt = bdim * bdim;
+    int64_t groups = int64_t(num_cus) * 2;
+    const int64_t cap = ((nt + 7) / 8) * 8;
+    if (groups > cap) groups = cap;
+    groups = ((groups + 7) / 8) * 8;
+    if (vec)
+        multiply_kernel<LEAF, true><<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist);
+    else
+        multiply_kernel<LEAF, false><<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist);
+    return hipGetLastError();
+}
+
+hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
+                           const int32_t* offsets, const int32_t* klist, bool vec, int num_cus, hipStream_t s) {
+    switch (leaf) {
+        case 32: return launch_mul<32>(a, b, c, n, bdim, offsets, klist, vec, num_cus, s);
+        case 64: return launch_mul<64>(a, b, c, n, bdim, offsets, klist, vec, num_cus, s);
+        case 128: return launch_mul<128>(a, b, c, n, bdim, offsets, klist, vec, num_cus, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace spamm

@@ -1,0 +1,331 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars:
+  - norms and pyramids: relative difference <= 1e-13 (both sum exact FP64
+    squares; only the summation order differs);
+  - skip masks: identical, except triples whose oracle norm product lies within
+    1e-12 relative of tau (either outcome is correct there);
+  - pairs: identical to the oracle's count (and to the closed form for the
+    algebraic-decay workload);
+  - C: every element within gamma_K * (|A||B| restricted to the kept pairs),
+    the FP32 accumulation bound with K = N terms and u = 2^-24, where the
+    restricted |A||B| is the oracle's SpAMM of |A| and |B| (same norms, so the
+    same mask); and relative Frobenius difference <= 1e-5 (the target for the
+    method is 1e-4).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from closed_forms import closed_form_pair_count
+from paper_2103_13042_amd import binding as sp
+from paper_2103_13042_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+U32 = 2.0**-24
+TIE = 1e-12
+REL_FRO = 1e-5
+
+
+def gpu(x: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def gamma32(k: int) -> float:
+    return k * U32 / (1.0 - k * U32)
+
+
+def mask_from_plan(offsets: torch.Tensor, klist: torch.Tensor, bd: int) -> np.ndarray:
+    off = offsets.cpu().numpy().astype(np.int64)
+    total = int(off[-1])
+    kl = klist[:total].cpu().numpy().astype(np.int64)
+    counts = np.diff(off)
+    tiles = np.repeat(np.arange(bd * bd), counts)
+    mask = np.zeros((bd * bd, bd), dtype=bool)
+    mask[tiles, kl] = True
+    # ascending and unique within each tile
+    if total:
+        same = tiles[1:] == tiles[:-1]
+        assert np.all(kl[1:][same] > kl[:-1][same])
+        assert kl.min() >= 0 and kl.max() < bd
+    return mask.reshape(bd, bd, bd)
+
+
+def oracle_products(a, b, leaf):
+    na, nb = oracle.leaf_norms(a, leaf), oracle.leaf_norms(b, leaf)
+    return na[:, None, :] * nb.T[None, :, :]  # [i, j, k] = nA[i,k] * nB[k,j]
+
+
+def off_tie(prod, tau):
+    if tau == 0.0 or math.isinf(tau):
+        return np.ones_like(prod, dtype=bool)
+    return np.abs(prod / tau - 1.0) > TIE
+
+
+def check_c(c_gpu: np.ndarray, a, b, tau, leaf, c_ref=None):
+    """C against the oracle: elementwise FP32 accumulation bound and rel. Frobenius."""
+    n = a.shape[0]
+    if c_ref is None:
+        c_ref, _, _ = oracle.spamm(a, b, tau, leaf)
+    abs_ref, _, _ = oracle.spamm(np.abs(a), np.abs(b), tau, leaf)
+    err = np.abs(c_gpu.astype(np.float64) - c_ref)
+    bound = gamma32(n) * abs_ref + 1e-38
+    worst = float(np.max(err - bound))
+    assert worst <= 0.0, f"elementwise bound exceeded by {worst:.3e}"
+    den = np.linalg.norm(c_ref)
+    rel = np.linalg.norm(c_gpu.astype(np.float64) - c_ref) / den if den > 0 else np.linalg.norm(c_gpu)
+    assert rel <= REL_FRO, rel
+    return rel
+
+
+# --------------------------------------------------------------------------
+# norm pass and pyramid
+
+
+@pytest.mark.parametrize(
+    "n,leaf,offset",
+    [(1024, 32, 0), (1000, 64, 0), (1001, 32, 0), (1024, 64, 1), (300, 128, 0), (77, 16, 0), (130, 7, 0), (5, 8, 0)],
+)
+def test_leaf_norms_match_oracle(n, leaf, offset):
+    a = inputs.exp_decay(n, 0.05, 0)
+    if offset:  # a view that is not 16-byte aligned takes the scalar load path
+        buf = torch.zeros(n * n + offset, dtype=torch.float32, device=DEV)
+        buf[offset:] = gpu(a).reshape(-1)
+        x = buf[offset:].view(n, n)
+    else:
+        x = gpu(a)
+    got = sp.norms(x, leaf).cpu().numpy()
+    want = oracle.leaf_norms(a, leaf)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+
+
+def test_leaf_norms_keep_fp32_subnormals():
+    # exp(-1.2*|i-j|) falls through the FP32 subnormal range (< 1.18e-38) a few
+    # tiles off the diagonal; those tiles must keep their tiny, non-zero norms.
+    n, leaf = 256, 32
+    a = inputs.exp_decay(n, 1.2, 3)
+    assert np.any((a > 0) & (a < np.finfo(np.float32).tiny))
+    got = sp.norms(gpu(a), leaf).cpu().numpy()
+    want = oracle.leaf_norms(a, leaf)
+    assert np.all((want > 0) == (got > 0))
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 64), (1100, 32), (20, 32), (8192, 64)])
+def test_pyramid_matches_oracle_and_is_monotone(n, leaf):
+    a = inputs.algebraic_decay_signed(n, 0) if n == 8192 else inputs.exp_decay(n, 0.03, 1)
+    flat = sp.pyramid(gpu(a), leaf)
+    got = [p.cpu().numpy() for p in sp.pyramid_levels(flat, n, leaf)]
+    want = oracle.pyramid(a, leaf)
+    assert len(got) == len(want)
+    for g, w in zip(got, want):
+        np.testing.assert_allclose(g, w, rtol=1e-13, atol=0)
+    # a parent is never below any of its children (exactly, in the GPU values)
+    for l in range(len(got) - 1):
+        kids = got[l + 1]
+        m = kids.shape[0] // 2
+        kmax = kids.reshape(m, 2, m, 2).max(axis=(1, 3))
+        assert np.all(got[l] >= kmax)
+
+
+# --------------------------------------------------------------------------
+# plan
+
+
+def _plan(a, b, leaf, tau):
+    n = a.shape[0]
+    ga, gb = gpu(a), gpu(b)
+    pa, pb = sp.pyramid(ga, leaf), sp.pyramid(gb, leaf)
+    offsets, klist, pairs = sp.plan(pa, pb, n, leaf, tau)
+    return offsets, klist, int(pairs.item())
+
+
+@pytest.mark.parametrize(
+    "n,leaf,tau,kind",
+    [
+        (1024, 32, 1e-6, "exp"),
+        (1024, 32, 1e-2, "exp"),
+        (1000, 64, 0.0, "exp"),
+        (1000, 64, 3.0, "rand"),
+        (4096, 32, 1e-6, "exp"),  # 128 x 128 grid: two k-chunks and pyramid skipping
+        (1100, 16, 1e-5, "exp"),  # 69 x 69 grid padded to 128
+    ],
+)
+def test_plan_mask_matches_oracle(n, leaf, tau, kind):
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.05, 0), inputs.exp_decay(n, 0.05, 1)
+    else:
+        a, b = inputs.uniform_pm1(n, 4), inputs.uniform_pm1(n, 5)
+    bd = oracle.bdim(n, leaf)
+    offsets, klist, pairs = _plan(a, b, leaf, tau)
+    got = mask_from_plan(offsets, klist, bd)
+    _, count, want = oracle.spamm(a, b, tau, leaf, products=False)
+    ok = off_tie(oracle_products(a, b, leaf), tau)
+    assert np.array_equal(got[ok], want[ok])
+    assert pairs == int(got.sum())
+    if ok.all():
+        assert pairs == count
+
+
+@pytest.mark.parametrize("tau", [1e-8, 1e-6, 1e-4])
+def test_plan_counts_algebraic_8192(tau, alg8192):
+    a, b = alg8192
+    offsets, klist, pairs = _plan(a, b, 64, tau)
+    want, _ = closed_form_pair_count(8192, 64, tau)
+    assert pairs == want
+    # masks of sampled tiles against the oracle's recursion
+    tiles = _sample_tiles(128, seed=7)
+    _, counts, omask = oracle.spamm_tiles(a, b, tau, 64, tiles, products=False)
+    got = mask_from_plan(offsets, klist, 128)
+    for t, (i, j) in enumerate(tiles):
+        assert np.array_equal(got[i, j], omask[t])
+
+
+# --------------------------------------------------------------------------
+# multiply and the whole path
+
+
+def test_multiply_c1_full_parity(c1):
+    a, b, c_ref, count = c1
+    c, pairs = sp.multiply(gpu(a), gpu(b), 1e-6, 32)
+    assert pairs == count
+    rel = check_c(c.cpu().numpy(), a, b, 1e-6, 32, c_ref=c_ref)
+    print(f"C1 rel Frobenius vs oracle: {rel:.3e}")
+
+
+@pytest.mark.parametrize(
+    "n,leaf,q,kind",
+    [
+        (1000, 64, 0.5, "rand"),   # ragged last tile row/column
+        (1001, 32, 0.3, "rand"),   # N not a multiple of 4: scalar load path
+        (777, 128, 0.6, "exp"),
+        (96, 32, 0.0, "rand"),     # tau = 0: the dense product
+        (20, 64, 0.0, "rand"),     # one tile smaller than the leaf
+        (520, 64, 0.9, "exp"),
+        (1024, 128, 0.7, "rand"),
+    ],
+)
+def test_multiply_matches_oracle(n, leaf, q, kind):
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.02, 8), inputs.exp_decay(n, 0.02, 9)
+    else:
+        a, b = inputs.uniform_pm1(n, 8), inputs.uniform_pm1(n, 9)
+    prod = oracle_products(a, b, leaf)
+    tau = float(np.quantile(prod, q)) if q > 0 else 0.0
+    c_ref, count, mask = oracle.spamm(a, b, tau, leaf)
+    c, pairs = sp.multiply(gpu(a), gpu(b), tau, leaf)
+    if off_tie(prod, tau).all():
+        assert pairs == count
+    check_c(c.cpu().numpy(), a, b, tau, leaf, c_ref=c_ref)
+
+
+def test_tau_zero_is_dense_and_counts_every_triple():
+    n, leaf = 512, 64
+    a, b = inputs.uniform_pm1(n, 1), inputs.uniform_pm1(n, 2)
+    c, pairs = sp.multiply(gpu(a), gpu(b), 0.0, leaf)
+    assert pairs == (n // leaf) ** 3
+    dense = a.astype(np.float64) @ b.astype(np.float64)
+    bound = gamma32(n) * (np.abs(a).astype(np.float64) @ np.abs(b).astype(np.float64))
+    assert np.all(np.abs(c.cpu().numpy() - dense) <= bound)
+
+
+def test_tau_above_every_product_gives_exact_zero():
+    n, leaf = 700, 64
+    a, b = inputs.uniform_pm1(n, 3), inputs.uniform_pm1(n, 4)
+    ga, gb = gpu(a), gpu(b)
+    big = 2.0 * float(np.linalg.norm(a.astype(np.float64)) * np.linalg.norm(b.astype(np.float64)))
+    for tau in (big, math.inf):
+        c = torch.full((n, n), 7.0, device=DEV)
+        _, pairs = sp.multiply(ga, gb, tau, leaf, c=c)
+        assert pairs == 0
+        assert torch.count_nonzero(c).item() == 0
+
+
+def test_zero_matrix():
+    n, leaf = 300, 32
+    z = torch.zeros((n, n), device=DEV)
+    b = gpu(inputs.uniform_pm1(n, 5))
+    c, pairs = sp.multiply(z, b, 1e-9, leaf)
+    assert pairs == 0 and torch.count_nonzero(c).item() == 0
+    c, pairs = sp.multiply(z, b, 0.0, leaf)  # 0 >= 0: every triple is multiplied
+    assert pairs == oracle.bdim(n, leaf) ** 3 and torch.count_nonzero(c).item() == 0
+
+
+def test_runs_are_bitwise_deterministic(c1):
+    a, b, _, _ = c1
+    ga, gb = gpu(a), gpu(b)
+    c1_, p1 = sp.multiply(ga, gb, 1e-6, 32)
+    c2_, p2 = sp.multiply(ga, gb, 1e-6, 32)
+    assert p1 == p2 and torch.equal(c1_, c2_)
+
+
+def test_staged_calls_equal_the_fused_call(c1):
+    a, b, _, _ = c1
+    ga, gb = gpu(a), gpu(b)
+    c_fused, pairs = sp.multiply(ga, gb, 1e-6, 32)
+    pa, pb = sp.pyramid(ga, 32), sp.pyramid(gb, 32)
+    offsets, klist, p = sp.plan(pa, pb, 1024, 32, 1e-6)
+    c_staged = sp.execute(ga, gb, 32, offsets, klist)
+    assert int(p.item()) == pairs
+    assert torch.equal(c_fused, c_staged)
+    o2, k2, p2 = sp.prepare(ga, gb, 1e-6, 32)
+    assert torch.equal(o2, offsets) and int(p2.item()) == pairs
+    assert torch.equal(k2[:pairs], klist[:pairs])
+    assert torch.equal(sp.execute(ga, gb, 32, o2, k2), c_fused)
+
+
+@pytest.mark.parametrize("tau", [1e-8, 1e-6, 1e-4])
+def test_algebraic_8192_full_size_sampled_tiles(tau, alg8192):
+    """The benchmark workload at full size and in the benchmark's launch
+    configuration: pair count against the closed form, sampled output tiles
+    against the oracle's recursion for those tiles."""
+    a, b = alg8192
+    n, leaf = 8192, 64
+    c, pairs = sp.multiply(gpu(a), gpu(b), tau, leaf)
+    assert pairs == closed_form_pair_count(n, leaf, tau)[0]
+    tiles = _sample_tiles(n // leaf, seed=11)
+    ct, counts, _ = oracle.spamm_tiles(a, b, tau, leaf, tiles)
+    abs_t, _, _ = oracle.spamm_tiles(np.abs(a), np.abs(b), tau, leaf, tiles)
+    cg = c.cpu().numpy()
+    num = den = 0.0
+    for t, (i, j) in enumerate(tiles):
+        blk = cg[i * leaf : (i + 1) * leaf, j * leaf : (j + 1) * leaf].astype(np.float64)
+        err = np.abs(blk - ct[t])
+        assert np.all(err <= gamma32(n) * abs_t[t] + 1e-38), (i, j)
+        num += float(np.sum((blk - ct[t]) ** 2))
+        den += float(np.sum(ct[t] ** 2))
+    assert math.sqrt(num / den) <= REL_FRO
+
+
+def _sample_tiles(bd: int, seed: int) -> np.ndarray:
+    """Diagonal and near-diagonal tiles, the corners, and a seeded random set."""
+    rng = np.random.default_rng(seed)
+    pick = {(i, i) for i in range(0, bd, max(1, bd // 16))}
+    pick |= {(i, min(bd - 1, i + d)) for i in range(0, bd, max(1, bd // 8)) for d in (1, 2, 5)}
+    pick |= {(0, bd - 1), (bd - 1, 0), (bd - 1, bd - 1)}
+    pick |= {tuple(int(v) for v in rng.integers(0, bd, 2)) for _ in range(24)}
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+# --------------------------------------------------------------------------
+# fixtures
+
+
+@pytest.fixture(scope="module")
+def c1():
+    a, b = inputs.workload_exp1024()
+    c_ref, count, _ = oracle.spamm(a, b, 1e-6, 32)
+    return a, b, c_ref, count
+
+
+@pytest.fixture(scope="module")
+def alg8192():
+    return inputs.workload_alg8192()
