@@ -54,7 +54,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
-    size_t sumsq[2], spyr[2], pyr[2], counts, masks, offsets, klist, pairs, total;
+    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, pairs, total;
 };
 
 Layout make_layout(const Geom& g) {
@@ -65,13 +65,15 @@ Layout make_layout(const Geom& g) {
         o = align_up(o + bytes);
         return at;
     };
-    for (int m = 0; m < 2; ++m) L.sumsq[m] = take(sizeof(double) * size_t(g.ntiles));
     for (int m = 0; m < 2; ++m) L.spyr[m] = take(sizeof(double) * size_t(g.pyr));
     for (int m = 0; m < 2; ++m) L.pyr[m] = take(sizeof(double) * size_t(g.pyr));
     L.counts = take(sizeof(int32_t) * size_t(g.ntiles));
+    L.bsums = take(sizeof(int32_t) * size_t(g.bdim) * size_t(g.nwords));
+    L.boffs = take(sizeof(int32_t) * size_t(g.bdim) * size_t(g.nwords));
     L.masks = take(sizeof(uint64_t) * size_t(g.ntiles) * size_t(g.nwords));
     L.offsets = take(sizeof(int32_t) * size_t(g.ntiles + 1));
     L.klist = take(sizeof(int32_t) * size_t(g.ntiles) * size_t(g.bdim));
+    L.pair_scratch = take(sizeof(int32_t) * size_t(g.ntiles) * size_t(g.bdim));
     L.pairs = take(sizeof(int64_t));
     L.total = o;
     return L;
@@ -128,17 +130,18 @@ spamm_status check_tau(double tau) {
 spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
                               hipStream_t s) {
     const Layout L = make_layout(g);
+    const int64_t leaf_level = spamm::level_offset(g.lv);
     spamm::NormJob nj{};
     spamm::PyramidJob pj{};
+    nj.ld = g.side;  // the norm pass writes the padded leaf level of both pyramids
     bool vec = (g.n % 4) == 0;
     for (int m = 0; m < nmat; ++m) {
         nj.x[m] = x[m];
-        nj.sumsq[m] = at<double>(ws, L.sumsq[m]);
-        nj.norms[m] = nullptr;
-        vec = vec && aligned16(x[m]);
-        pj.sumsq[m] = nj.sumsq[m];
         pj.spyr[m] = at<double>(ws, L.spyr[m]);
         pj.pyr[m] = pyr_out[m];
+        nj.sumsq[m] = pj.spyr[m] + leaf_level;
+        nj.norms[m] = pj.pyr[m] + leaf_level;
+        vec = vec && aligned16(x[m]);
     }
     spamm_status st = hip_check(spamm::launch_leaf_norms(nj, nmat, g.n, g.leaf, vec, s), "leaf norm kernel");
     if (st != SPAMM_OK) return st;
@@ -150,12 +153,15 @@ spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, dou
     const Layout L = make_layout(g);
     uint64_t* masks = at<uint64_t>(ws, L.masks);
     int32_t* counts = at<int32_t>(ws, L.counts);
-    spamm_status st =
-        hip_check(spamm::launch_plan_mask(pa, pb, g.bdim, g.lv, tau, masks, counts, s), "plan mask kernel");
+    int32_t* bsums = at<int32_t>(ws, L.bsums);
+    int32_t* boffs = at<int32_t>(ws, L.boffs);
+    spamm_status st = hip_check(spamm::launch_plan_mask(pa, pb, g.bdim, g.lv, tau, masks, counts, bsums, s),
+                                "plan mask kernel");
     if (st != SPAMM_OK) return st;
-    st = hip_check(spamm::launch_plan_scan(counts, g.ntiles, offsets, pairs, s), "plan scan kernel");
+    st = hip_check(spamm::launch_plan_scan(bsums, g.bdim * g.nwords, boffs, offsets, g.ntiles, pairs, s),
+                   "plan scan kernel");
     if (st != SPAMM_OK) return st;
-    return hip_check(spamm::launch_plan_fill(masks, offsets, g.ntiles, g.nwords, klist, s), "plan fill kernel");
+    return hip_check(spamm::launch_plan_fill(masks, counts, boffs, g.bdim, offsets, klist, s), "plan fill kernel");
 }
 
 spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const float* c) {
@@ -204,6 +210,7 @@ spamm_status spamm_norms(const float* x, int64_t n, int32_t leaf, double* norms,
     nj.x[0] = x;
     nj.sumsq[0] = nullptr;
     nj.norms[0] = norms;
+    nj.ld = g.bdim;
     const bool vec = (n % 4) == 0 && aligned16(x);
     return hip_check(spamm::launch_leaf_norms(nj, 1, n, leaf, vec, static_cast<hipStream_t>(stream)),
                      "leaf norm kernel");
@@ -251,7 +258,8 @@ spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t le
     if ((st = check_grid(g)) != SPAMM_OK) return st;
     if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
     const bool vec = (n % 4) == 0 && aligned16(a) && aligned16(b);
-    return hip_check(spamm::launch_multiply(a, b, c, n, leaf, g.bdim, offsets, klist, vec, device_cus(),
+    int32_t* scratch = at<int32_t>(workspace, make_layout(g).pair_scratch);
+    return hip_check(spamm::launch_multiply(a, b, c, n, leaf, g.bdim, offsets, klist, scratch, vec, device_cus(),
                                             static_cast<hipStream_t>(stream)),
                      "multiply kernel");
 }

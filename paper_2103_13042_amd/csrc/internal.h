@@ -15,14 +15,16 @@ __host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << 
 // kernels (A and B of one product).
 struct NormJob {
     const float* x[2];
-    double* sumsq[2];  // [bdim*bdim] leaf sums of squares, or null
-    double* norms[2];  // [bdim*bdim] leaf norms, or null
+    double* sumsq[2];  // leaf sums of squares, row stride ld, or null
+    double* norms[2];  // leaf norms, row stride ld, or null
+    int64_t ld;        // row stride of the outputs (bdim, or the padded pyramid side)
 };
 
+// The leaf level of both pyramids is written by the norm pass (stride = side);
+// the pyramid kernel zeroes its padding tiles and builds the levels above.
 struct PyramidJob {
-    const double* sumsq[2];  // [bdim*bdim] leaf sums of squares
-    double* spyr[2];         // [pyramid] sums of squares at every level (scratch)
-    double* pyr[2];          // [pyramid] norms at every level (output)
+    double* spyr[2];  // [pyramid] sums of squares at every level (scratch)
+    double* pyr[2];   // [pyramid] norms at every level (output)
 };
 
 // Norm pass: leaf sums of squares / norms of nmat matrices.
@@ -31,17 +33,22 @@ hipError_t launch_leaf_norms(const NormJob& job, int nmat, int64_t n, int32_t le
 // Pyramid: bottom-up quadtree of sums of squares and norms for nmat matrices.
 hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv, hipStream_t s);
 
-// Plan: per output tile, the ballot bitmap of kept k (words of 64) and its count V.
+// Plan: per output tile, the ballot bitmap of kept k (words of 64) and its
+// count V; per block of 64 tiles (i, 64*jb ..) the sum of V (block b = i*nw + jb).
 hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
-                            uint64_t* masks, int32_t* counts, hipStream_t s);
-// Plan: exclusive scan of V into offsets, total into offsets[T] and *pairs.
-hipError_t launch_plan_scan(const int32_t* counts, int64_t ntiles, int32_t* offsets, int64_t* pairs, hipStream_t s);
-// Plan: compaction of the bitmaps into ascending k-lists at the scanned offsets.
-hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* offsets, int64_t ntiles, int nwords,
-                            int32_t* klist, hipStream_t s);
+                            uint64_t* masks, int32_t* counts, int32_t* block_sums, hipStream_t s);
+// Plan: exclusive scan of the block sums; the total goes to offsets[T] and *pairs.
+hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t* block_offsets, int32_t* offsets,
+                            int64_t ntiles, int64_t* pairs, hipStream_t s);
+// Plan: per tile offset (block offset + prefix inside the block) and the
+// compaction of its bitmap into an ascending k-list.
+hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* counts, const int32_t* block_offsets,
+                            int64_t bdim, int32_t* offsets, int32_t* klist, hipStream_t s);
 
 // Multiply: persistent, cost-balanced multiply of the kept pairs into C.
+// pair_scratch holds bdim^3 int32 (each group's packed (tile, k) pairs).
 hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                           const int32_t* offsets, const int32_t* klist, bool vec, int num_cus, hipStream_t s);
+                           const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
+                           int num_cus, hipStream_t s);
 
 }  // namespace spamm

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, i
     for (int off = 1; off < G; off <<= 1) s += __shfl_xor(s, off);
     const int64_t tj = col / LEAF;
     if ((threadIdx.x % G) == 0 && tj < bdim) {
-        const int64_t t = int64_t(blockIdx.y) * bdim + tj;
+        const int64_t t = int64_t(blockIdx.y) * job.ld + tj;
         if (job.sumsq[m]) job.sumsq[m][t] = s;
         if (job.norms[m]) job.norms[m][t] = sqrt(s);
     }
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_generic_kernel(NormJo
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int w = 0; w < kNormThreads / 64; ++w) s += partial[w];
-        const int64_t t = ti * bdim + tj;
+        const int64_t t = ti * job.ld + tj;
         if (job.sumsq[m]) job.sumsq[m][t] = s;
         if (job.norms[m]) job.norms[m][t] = sqrt(s);
     }
@@ -147,17 +147,17 @@ constexpr int kPyrThreads = 1024;
 
 __global__ __launch_bounds__(kPyrThreads) void pyramid_kernel(PyramidJob job, int64_t bdim, int lv) {
     const int m = blockIdx.x;
-    const double* __restrict__ leaf_s = job.sumsq[m];
     double* __restrict__ sp = job.spyr[m];
     double* __restrict__ np = job.pyr[m];
     const int64_t side = int64_t(1) << lv;
-    {
+    if (bdim < side) {  // padding tiles of the leaf level: norm 0
         const int64_t base = level_offset(lv);
         for (int64_t idx = threadIdx.x; idx < side * side; idx += kPyrThreads) {
             const int64_t i = idx >> lv, j = idx & (side - 1);
-            const double v = (i < bdim && j < bdim) ? leaf_s[i * bdim + j] : 0.0;
-            sp[base + idx] = v;
-            np[base + idx] = sqrt(v);
+            if (i >= bdim || j >= bdim) {
+                sp[base + idx] = 0.0;
+                np[base + idx] = 0.0;
+            }
         }
     }
     for (int l = lv - 1; l >= 0; --l) {
@@ -193,8 +193,10 @@ constexpr int kPlanThreads = 256;
 __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* __restrict__ pyr_a,
                                                                  const double* __restrict__ pyr_b, int64_t bdim,
                                                                  int lv, double tau, uint64_t* __restrict__ masks,
-                                                                 int32_t* __restrict__ counts) {
+                                                                 int32_t* __restrict__ counts,
+                                                                 int32_t* __restrict__ block_sums) {
     __shared__ double sb[64][65];
+    __shared__ int wsum[kPlanThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = blockIdx.y, j0 = int64_t(blockIdx.x) * 64;
     const int64_t side = int64_t(1) << lv;
@@ -222,15 +224,23 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
             }
             continue;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * 64; e += kPlanThreads) {
-            const int r = e >> 6, cc = e & 63;
-            const int64_t k = int64_t(c) * 64 + r, j = j0 + cc;
-            sb[r][cc] = (k < side && j < side) ? lb[k * side + j] : 0.0;
+        // stage the chunk's 64 x 64 B norms: all loads first, then the LDS writes
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = threadIdx.x + u * kPlanThreads;
+            const int64_t k = int64_t(c) * 64 + (e >> 6), j = j0 + (e & 63);
+            v[u] = (k < side && j < side) ? lb[k * side + j] : 0.0;
         }
-        __syncthreads();
         const int64_t k = int64_t(c) * 64 + lane;
         const double a = k < side ? la[i * side + k] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = threadIdx.x + u * kPlanThreads;
+            sb[e >> 6][e & 63] = v[u];
+        }
+        __syncthreads();
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int jj = wave + 4 * u;
@@ -242,35 +252,41 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
             cnt[u] += __popcll(mk);
         }
     }
-    if (lane == 0) {
+    int tot = 0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int64_t j = j0 + wave + 4 * u;
-            if (j < bdim) counts[i * bdim + j] = cnt[u];
+    for (int u = 0; u < 16; ++u) {
+        const int64_t j = j0 + wave + 4 * u;
+        if (j < bdim) {
+            if (lane == 0) counts[i * bdim + j] = cnt[u];
+            tot += cnt[u];
         }
     }
+    if (lane == 0) wsum[wave] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) block_sums[i * nw + blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
-                            uint64_t* masks, int32_t* counts, hipStream_t s) {
-    dim3 grid(unsigned((bdim + 63) / 64), unsigned(bdim));
-    plan_mask_kernel<<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts);
+                            uint64_t* masks, int32_t* counts, int32_t* block_sums, hipStream_t s) {
+    dim3 grid{unsigned((bdim + 63) / 64), unsigned(bdim), 1u};
+    plan_mask_kernel<<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts, block_sums);
     return hipGetLastError();
 }
 
-// Exclusive scan of the per-tile counts: one block of 1024 threads, each
+// Exclusive scan of the block sums (one per 64 output tiles): one block, each
 // thread a contiguous segment, wave scans with shuffles, then across waves.
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 256;
 
-__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* __restrict__ counts, int64_t nt,
-                                                                 int32_t* __restrict__ offsets,
+__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* __restrict__ block_sums,
+                                                                 int64_t nb, int32_t* __restrict__ block_offsets,
+                                                                 int32_t* __restrict__ offsets, int64_t nt,
                                                                  int64_t* __restrict__ pairs) {
     __shared__ int64_t wsum[kScanThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t seg = (nt + kScanThreads - 1) / kScanThreads;
-    const int64_t b = tid * seg, e = (b + seg < nt ? b + seg : nt);
+    const int64_t seg = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t b = tid * seg, e = (b + seg < nb ? b + seg : nb);
     int64_t local = 0;
-    for (int64_t t = b; t < e; ++t) local += counts[t];
+    for (int64_t t = b; t < e; ++t) local += block_sums[t];
     int64_t incl = local;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -279,12 +295,11 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* 
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int64_t wbase = 0;
-    for (int w = 0; w < wave; ++w) wbase += wsum[w];
-    int64_t run = wbase + incl - local;
+    int64_t run = incl - local;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
     for (int64_t t = b; t < e; ++t) {
-        offsets[t] = int32_t(run);
-        run += counts[t];
+        block_offsets[t] = int32_t(run);
+        run += block_sums[t];
     }
     if (tid == kScanThreads - 1) {
         int64_t total = 0;
@@ -294,20 +309,32 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* 
     }
 }
 
-hipError_t launch_plan_scan(const int32_t* counts, int64_t ntiles, int32_t* offsets, int64_t* pairs, hipStream_t s) {
-    plan_scan_kernel<<<1, kScanThreads, 0, s>>>(counts, ntiles, offsets, pairs);
+hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t* block_offsets, int32_t* offsets,
+                            int64_t ntiles, int64_t* pairs, hipStream_t s) {
+    plan_scan_kernel<<<1, kScanThreads, 0, s>>>(block_sums, nblocks, block_offsets, offsets, ntiles, pairs);
     return hipGetLastError();
 }
 
-// Compaction: one wave per output tile; a lane whose bit is set writes its k at
-// the tile's offset plus the number of set bits below it (ascending k).
+// One wave per output tile t = (i, j): its offset is the offset of its block
+// of 64 tiles plus the counts of the tiles before it in the block (a masked
+// wave sum); then every lane whose bit is set writes its k at the offset plus
+// the number of set bits below it (ascending k).
 __global__ __launch_bounds__(256) void plan_fill_kernel(const uint64_t* __restrict__ masks,
-                                                        const int32_t* __restrict__ offsets, int64_t nt, int nw,
-                                                        int32_t* __restrict__ klist) {
+                                                        const int32_t* __restrict__ counts,
+                                                        const int32_t* __restrict__ block_offsets, int64_t bdim,
+                                                        int32_t* __restrict__ offsets, int32_t* __restrict__ klist) {
     const int lane = threadIdx.x & 63;
+    const int64_t nt = bdim * bdim;
     const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (t >= nt) return;
-    int64_t base = offsets[t];
+    const int nw = int((bdim + 63) / 64);
+    const int64_t i = t / bdim, j = t % bdim, jb = j >> 6;
+    const int64_t jl = (jb * 64 + lane < bdim) ? jb * 64 + lane : -1;  // the block's tile for this lane
+    int before = (jl >= 0 && (jl & 63) < (j & 63)) ? counts[i * bdim + jl] : 0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) before += __shfl_xor(before, off);
+    int64_t base = int64_t(block_offsets[i * nw + jb]) + before;
+    if (lane == 0) offsets[t] = int32_t(base);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int w = 0; w < nw; ++w) {
         const uint64_t m = masks[t * nw + w];
@@ -316,9 +343,10 @@ __global__ __launch_bounds__(256) void plan_fill_kernel(const uint64_t* __restri
     }
 }
 
-hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* offsets, int64_t ntiles, int nwords,
-                            int32_t* klist, hipStream_t s) {
-    plan_fill_kernel<<<unsigned((ntiles + 3) / 4), 256, 0, s>>>(masks, offsets, ntiles, nwords, klist);
+hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* counts, const int32_t* block_offsets,
+                            int64_t bdim, int32_t* offsets, int32_t* klist, hipStream_t s) {
+    const int64_t nt = bdim * bdim;
+    plan_fill_kernel<<<unsigned((nt + 3) / 4), 256, 0, s>>>(masks, counts, block_offsets, bdim, offsets, klist);
     return hipGetLastError();
 }
 
@@ -333,31 +361,55 @@ hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* offsets, int64
 // congruent mod 8) own neighbouring ranges and share A/B tiles in that XCD's
 // L2.
 //
-// A group runs the flat stream of its (pair, k-chunk) items through a two-stage
-// LDS pipeline: the global loads of item it+1 are in flight while the four
-// waves multiply item it out of LDS.  Wave w computes the (w>>1, w&1) quadrant
-// of the output tile with FP32 MFMA: 32x32x2 for quadrants of 32 or 64, 16x16x4
-// for quadrants of 16.  The sum over a pair's k is re-indexed so that each lane
-// reads 4 consecutive A values with one LDS load: MFMA step s, lane group g
-// uses k = G*s + g, and A is stored in LDS at column (k % G) * (KC/G) + k / G.
-// Tiles are finished in ascending k, then written from the accumulators.
+// A group first writes its pairs as packed (ti << 20 | tj << 10 | k) words into
+// pair_scratch and streams them through a 128-entry LDS ring, refilled 64 at a
+// time right after a stage commit (when no tile load is in flight), so the
+// tile-load prefetch never waits on an index load.  The flat stream of (pair, k-chunk)
+// items then runs through two register sets and two LDS stages: while the four
+// waves multiply item it out of LDS, item it+1 sits in registers waiting to be
+// stored to the other stage and the global loads of item it+2 are in flight.
+// Tile loads are unconditional (out-of-range lanes read a valid address and
+// select zero) so the wait before storing item it+1 leaves item it+2's loads
+// outstanding.  Wave w computes
+// the (w>>1, w&1) quadrant of the output tile with FP32 MFMA: 32x32x2 for
+// quadrants of 32 or 64, 16x16x4 for quadrants of 16.  In MFMA step s, lane
+// group g takes k = g*(KC/G) + s, so a lane reads 4 consecutive A operands
+// with one 16-byte LDS load; B rows are XOR-swizzled by lane group so the G
+// groups read disjoint LDS banks.  Tiles are finished in ascending k and written
+// from the accumulators; tiles without pairs are written as zeros.
 
 constexpr int kMulThreads = 256;
 constexpr int kPairCost = 4;
+constexpr int kIdxBits = 10;  // packed pair = ti << 20 | tj << 10 | k  (all < 1024)
+constexpr int32_t kIdxMask = (1 << kIdxBits) - 1;
+constexpr int kRing = 512;  // packed pairs held in LDS (a power of two)
 
+// Tile shapes per leaf: MFMA edge, k per pipeline stage, workgroups per CU.
+#ifndef SPAMM_KC64
+#define SPAMM_KC64 64
+#endif
+#ifndef SPAMM_OCC64
+#define SPAMM_OCC64 2
+#endif
+#ifndef SPAMM_OCC32
+#define SPAMM_OCC32 2
+#endif
+#ifndef SPAMM_OCC128
+#define SPAMM_OCC128 2
+#endif
 template <int LEAF>
 struct MulCfg;
 template <>
 struct MulCfg<32> {
-    static constexpr int MF = 16, KC = 32;
+    static constexpr int MF = 16, KC = 32, OCC = SPAMM_OCC32;
 };
 template <>
 struct MulCfg<64> {
-    static constexpr int MF = 32, KC = 64;
+    static constexpr int MF = 32, KC = SPAMM_KC64, OCC = SPAMM_OCC64;
 };
 template <>
 struct MulCfg<128> {
-    static constexpr int MF = 32, KC = 32;
+    static constexpr int MF = 32, KC = 32, OCC = SPAMM_OCC128;
 };
 
 template <int LEAF>
@@ -370,7 +422,8 @@ struct MulGeom {
     static constexpr int SPC = KC / G;            // MFMA steps per stage
     static constexpr int NCH = LEAF / KC;         // stages per leaf pair
     static constexpr int AST = KC + 4;            // A stage row stride (floats)
-    static constexpr int BST = LEAF + 4;          // B stage row stride (floats)
+    static constexpr int BST = LEAF < 64 ? 64 : LEAF;  // B stage row stride (room for the swizzle)
+    static constexpr int SWZ = 64 / G;            // B column swizzle unit
     static constexpr int ASZ = LEAF * AST;
     static constexpr int BSZ = KC * BST;
     static constexpr int STAGE = ASZ + BSZ;
@@ -418,11 +471,12 @@ __device__ __forceinline__ int64_t partition_start(const int32_t* __restrict__ o
 }
 
 template <int LEAF, bool VEC>
-__global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* __restrict__ A,
+__global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_kernel(const float* __restrict__ A,
                                                                   const float* __restrict__ B, float* __restrict__ C,
                                                                   int64_t n, int64_t bdim,
                                                                   const int32_t* __restrict__ off,
-                                                                  const int32_t* __restrict__ klist) {
+                                                                  const int32_t* __restrict__ klist,
+                                                                  int32_t* pairs) {
     using Gm = MulGeom<LEAF>;
     using M = Mfma<Gm::MF>;
     __shared__ __attribute__((aligned(16))) float lds[2 * Gm::STAGE];
@@ -443,6 +497,27 @@ __global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* _
     const int64_t q_begin = off[t_begin], q_end = off[t_end];
     const int64_t nitems = (q_end - q_begin) * Gm::NCH;
 
+    // packed (ti, tj, k) of every pair of the range
+    for (int64_t q = q_begin + tid; q < q_end; q += kMulThreads) {
+        int64_t lo = t_begin, hi = t_end - 1;  // tile of q: last t with off[t] <= q
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= q)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int32_t ti = int32_t(lo / bdim), tj = int32_t(lo - int64_t(ti) * bdim);
+        pairs[q] = (ti << (2 * kIdxBits)) | (tj << kIdxBits) | klist[q];
+    }
+    __syncthreads();
+    __shared__ int32_t ring[kRing];
+    const int64_t npairs = q_end - q_begin;
+    for (int e = tid; e < kRing; e += kMulThreads) ring[e] = e < npairs ? pairs[q_begin + e] : 0;
+    __syncthreads();
+    int64_t rbase = 0;  // ring holds pairs [rbase, rbase + kRing)
+    auto pk_of_item = [&](int64_t it) -> int32_t { return ring[(it / Gm::NCH) & (kRing - 1)]; };
+
     typename M::acc_t acc[Gm::NB][Gm::NB];
     auto zero_acc = [&]() {
 #pragma unroll
@@ -452,30 +527,27 @@ __global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* _
 #pragma unroll
                 for (int r = 0; r < Gm::ACC; ++r) acc[a][b][r] = 0.0f;
     };
-    auto store_tile = [&](int64_t t) {
-        const int64_t ti = t / bdim, tj = t % bdim;
+    auto store_tile = [&](int32_t ti, int32_t tj) {
 #pragma unroll
         for (int a = 0; a < Gm::NB; ++a)
 #pragma unroll
             for (int b = 0; b < Gm::NB; ++b)
 #pragma unroll
                 for (int r = 0; r < Gm::ACC; ++r) {
-                    const int64_t row = ti * LEAF + wr * Gm::QM + a * Gm::MF + M::row(r, lane);
-                    const int64_t col = tj * LEAF + wc * Gm::QM + b * Gm::MF + M::col(r, lane);
+                    const int64_t row = int64_t(ti) * LEAF + wr * Gm::QM + a * Gm::MF + M::row(r, lane);
+                    const int64_t col = int64_t(tj) * LEAF + wc * Gm::QM + b * Gm::MF + M::col(r, lane);
                     if (row < n && col < n) C[row * n + col] = acc[a][b][r];
                 }
     };
 
-    // global -> register staging of one (pair, chunk) item
-    f4 ra[Gm::NV], rb[Gm::NV];
-    int64_t pt = t_begin;  // tile of the item being fetched
-    auto fetch = [&](int64_t it) {
-        const int64_t q = q_begin + it / Gm::NCH;
-        const int ch = int(it % Gm::NCH);
-        while (off[pt + 1] <= q) ++pt;
-        const int64_t ti = pt / bdim, tj = pt % bdim, kt = klist[q];
+    // global -> register staging of one (pair, chunk) item; every lane issues
+    // every load (clamped to a valid address) and zeroes what lies outside C
+    auto fetch = [&](int32_t pk, int ch, f4 (&ra)[Gm::NV], f4 (&rb)[Gm::NV]) {
+        const int64_t ti = (uint32_t(pk) >> (2 * kIdxBits)) & kIdxMask, tj = (uint32_t(pk) >> kIdxBits) & kIdxMask,
+                      kt = uint32_t(pk) & kIdxMask;
         const int64_t arow0 = ti * LEAF, acol0 = kt * LEAF + ch * Gm::KC;
         const int64_t brow0 = kt * LEAF + ch * Gm::KC, bcol0 = tj * LEAF;
+        const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int v = 0; v < Gm::NV; ++v) {
             const int e = tid + v * kMulThreads;
@@ -483,27 +555,37 @@ __global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* _
                 const int r = e / (Gm::KC / 4), c4 = e % (Gm::KC / 4);
                 const int64_t row = arow0 + r, col = acol0 + 4 * c4;
                 if (VEC) {
-                    ra[v] = (row < n && col < n) ? *reinterpret_cast<const f4*>(A + row * n + col) : f4{0, 0, 0, 0};
+                    const bool in = row < n && col < n;
+                    const f4 x = *reinterpret_cast<const f4*>(A + (in ? row * n + col : 0));
+                    ra[v] = in ? x : zero;
                 } else {
 #pragma unroll
-                    for (int q4 = 0; q4 < 4; ++q4)
-                        ra[v][q4] = (row < n && col + q4 < n) ? A[row * n + col + q4] : 0.0f;
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const bool in = row < n && col + q4 < n;
+                        const float x = A[in ? row * n + col + q4 : 0];
+                        ra[v][q4] = in ? x : 0.0f;
+                    }
                 }
             }
             {
                 const int r = e / (LEAF / 4), c4 = e % (LEAF / 4);
                 const int64_t row = brow0 + r, col = bcol0 + 4 * c4;
                 if (VEC) {
-                    rb[v] = (row < n && col < n) ? *reinterpret_cast<const f4*>(B + row * n + col) : f4{0, 0, 0, 0};
+                    const bool in = row < n && col < n;
+                    const f4 x = *reinterpret_cast<const f4*>(B + (in ? row * n + col : 0));
+                    rb[v] = in ? x : zero;
                 } else {
 #pragma unroll
-                    for (int q4 = 0; q4 < 4; ++q4)
-                        rb[v][q4] = (row < n && col + q4 < n) ? B[row * n + col + q4] : 0.0f;
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const bool in = row < n && col + q4 < n;
+                        const float x = B[in ? row * n + col + q4 : 0];
+                        rb[v][q4] = in ? x : 0.0f;
+                    }
                 }
             }
         }
     };
-    auto commit = [&](int stage) {
+    auto commit = [&](int stage, const f4 (&ra)[Gm::NV], const f4 (&rb)[Gm::NV]) {
         float* sa = lds + stage * Gm::STAGE;
         float* sb = sa + Gm::ASZ;
 #pragma unroll
@@ -511,21 +593,19 @@ __global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* _
             const int e = tid + v * kMulThreads;
             {
                 const int r = e / (Gm::KC / 4), c4 = e % (Gm::KC / 4);
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int k = 4 * c4 + q4;
-                    sa[r * Gm::AST + (k % Gm::G) * Gm::SPC + k / Gm::G] = ra[v][q4];
-                }
+                *reinterpret_cast<f4*>(sa + r * Gm::AST + 4 * c4) = ra[v];
             }
             {
                 const int r = e / (LEAF / 4), c4 = e % (LEAF / 4);
-                *reinterpret_cast<f4*>(sb + r * Gm::BST + 4 * c4) = rb[v];
+                const int swz = ((r / Gm::SPC) % Gm::G) * Gm::SWZ;
+                *reinterpret_cast<f4*>(sb + r * Gm::BST + ((4 * c4) ^ swz)) = rb[v];
             }
         }
     };
     auto compute = [&](int stage) {
         const float* sa = lds + stage * Gm::STAGE;
-        const float* sb = sa + Gm::ASZ;
+        const float* sb = sa + Gm::ASZ + g * Gm::SPC * Gm::BST;
+        const int swz = g * Gm::SWZ;
 #pragma unroll
         for (int q = 0; q < Gm::SPC / 4; ++q) {
             f4 av[Gm::NB];
@@ -538,7 +618,8 @@ __global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* _
                 const int s = 4 * q + u;
                 float bv[Gm::NB];
 #pragma unroll
-                for (int b = 0; b < Gm::NB; ++b) bv[b] = sb[(Gm::G * s + g) * Gm::BST + wc * Gm::QM + b * Gm::MF + ir];
+                for (int b = 0; b < Gm::NB; ++b)
+                    bv[b] = sb[s * Gm::BST + ((wc * Gm::QM + b * Gm::MF + ir) ^ swz)];
 #pragma unroll
                 for (int a = 0; a < Gm::NB; ++a)
 #pragma unroll
@@ -547,55 +628,82 @@ __global__ __launch_bounds__(kMulThreads, 2) void multiply_kernel(const float* _
         }
     };
 
-    zero_acc();
+    // output tile being accumulated: linear index t, coordinates (ti, tj);
+    // tiles before it are written
     int64_t t = t_begin;
-    if (nitems > 0) {
-        fetch(0);
-        commit(0);
-    }
-    for (int64_t it = 0; it < nitems; ++it) {
-        if (it % Gm::NCH == 0) {
-            const int64_t q = q_begin + it / Gm::NCH;
-            while (off[t + 1] <= q) {  // tile t is complete (or has no pairs)
-                store_tile(t);
-                zero_acc();
-                ++t;
-            }
-        }
-        const bool more = it + 1 < nitems;
-        if (more) fetch(it + 1);
-        __syncthreads();
-        compute(int(it & 1));
-        if (more) commit(int((it + 1) & 1));
-    }
-    while (t < t_end) {
-        store_tile(t);
+    int32_t ti = int32_t(t_begin / bdim), tj = int32_t(t_begin - int64_t(ti) * bdim);
+    auto advance_tile = [&]() {
+        store_tile(ti, tj);
         zero_acc();
         ++t;
+        if (++tj == bdim) {
+            tj = 0;
+            ++ti;
+        }
+    };
+    // one item of the stream: R_free receives item it+2, R_next (item it+1)
+    // goes to LDS after the multiply of item it
+    f4 ra0[Gm::NV], rb0[Gm::NV], ra1[Gm::NV], rb1[Gm::NV];
+    auto step = [&](int64_t it, f4 (&fa)[Gm::NV], f4 (&fb)[Gm::NV], const f4 (&na)[Gm::NV],
+                    const f4 (&nb)[Gm::NV]) {
+        const int32_t pk = pk_of_item(it);
+        const int64_t t_it =
+            int64_t((uint32_t(pk) >> (2 * kIdxBits)) & kIdxMask) * bdim + ((uint32_t(pk) >> kIdxBits) & kIdxMask);
+        while (t < t_it) advance_tile();  // tile t is complete (or has no pairs)
+        const int64_t i2 = it + 2 < nitems ? it + 2 : nitems - 1;  // past the end: a harmless reload
+        fetch(pk_of_item(i2), int(i2 % Gm::NCH), fa, fb);
+        __syncthreads();
+        compute(int(it & 1));
+        if (it + 1 < nitems) commit(int((it + 1) & 1), na, nb);
+        // every wave is past pair (it+1)/NCH - 1: recycle the older half of the ring
+        if ((it + 1) / Gm::NCH >= rbase + kRing / 2) {
+            for (int e = tid; e < kRing / 2; e += kMulThreads) {
+                const int64_t p = rbase + kRing + e;
+                ring[(rbase + e) & (kRing - 1)] = p < npairs ? pairs[q_begin + p] : 0;
+            }
+            rbase += kRing / 2;
+        }
+    };
+    zero_acc();
+    if (nitems > 0) {
+        fetch(pk_of_item(0), 0, ra0, rb0);
+        const int64_t i1 = nitems > 1 ? 1 : 0;
+        fetch(pk_of_item(i1), int(i1 % Gm::NCH), ra1, rb1);
+        commit(0, ra0, rb0);
     }
+    for (int64_t it = 0; it < nitems; it += 2) {
+        step(it, ra0, rb0, ra1, rb1);
+        if (it + 1 >= nitems) break;
+        step(it + 1, ra1, rb1, ra0, rb0);
+    }
+    while (t < t_end) advance_tile();
 }
 
 template <int LEAF>
 static hipError_t launch_mul(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
-                             const int32_t* offsets, const int32_t* klist, bool vec, int num_cus, hipStream_t s) {
+                             const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
+                             int num_cus, hipStream_t s) {
     const int64_t nt = bdim * bdim;
-    int64_t groups = int64_t(num_cus) * 2;
+    int64_t groups = int64_t(num_cus) * MulCfg<LEAF>::OCC;
     const int64_t cap = ((nt + 7) / 8) * 8;
     if (groups > cap) groups = cap;
     groups = ((groups + 7) / 8) * 8;
     if (vec)
-        multiply_kernel<LEAF, true><<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist);
+        multiply_kernel<LEAF, true>
+            <<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist, pair_scratch);
     else
-        multiply_kernel<LEAF, false><<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist);
+        multiply_kernel<LEAF, false>
+            <<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist, pair_scratch);
     return hipGetLastError();
 }
 
 hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                           const int32_t* offsets, const int32_t* klist, bool vec, int num_cus, hipStream_t s) {
+                           const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
+                           int num_cus, hipStream_t s) {
     switch (leaf) {
-        case 32: return launch_mul<32>(a, b, c, n, bdim, offsets, klist, vec, num_cus, s);
-        case 64: return launch_mul<64>(a, b, c, n, bdim, offsets, klist, vec, num_cus, s);
-        case 128: return launch_mul<128>(a, b, c, n, bdim, offsets, klist, vec, num_cus, s);
+        case 32: return launch_mul<32>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
+        case 64: return launch_mul<64>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
+        case 128: return launch_mul<128>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }

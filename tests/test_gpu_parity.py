@@ -237,6 +237,25 @@ def test_tau_zero_is_dense_and_counts_every_triple():
     assert np.all(np.abs(c.cpu().numpy() - dense) <= bound)
 
 
+@pytest.mark.parametrize("n,leaf", [(4096, 64), (2048, 32), (8192, 128)])
+def test_many_pairs_per_workgroup(n, leaf):
+    """tau = 0 on a dense random matrix: every workgroup of the multiply owns
+    hundreds of pairs, so its pair stream wraps around its LDS ring several
+    times.  At tau = 0 SpAMM is the dense product (pinned for the oracle), so
+    the reference is the FP64 product of the same FP32 inputs; every element is
+    checked against the FP32 accumulation bound."""
+    a, b = inputs.uniform_pm1(n, 21), inputs.uniform_pm1(n, 22)
+    ga, gb = gpu(a), gpu(b)
+    c, pairs = sp.multiply(ga, gb, 0.0, leaf)
+    assert pairs == (n // leaf) ** 3
+    ref = ga.double() @ gb.double()
+    bound = gamma32(n) * (ga.abs().double() @ gb.abs().double())
+    excess = float(((c.double() - ref).abs() - bound).max())
+    assert excess <= 0.0, excess
+    rel = float(torch.linalg.norm(c.double() - ref) / torch.linalg.norm(ref))
+    assert rel <= REL_FRO, rel
+
+
 def test_tau_above_every_product_gives_exact_zero():
     n, leaf = 700, 64
     a, b = inputs.uniform_pm1(n, 3), inputs.uniform_pm1(n, 4)
