@@ -18,7 +18,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 LIB = PKG / "libspamm.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "api.hip"]
+SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "api.hip"]
 ARCH = "gfx950"
 
 
@@ -42,7 +42,7 @@ def compile_flags() -> list[str]:
     ]
 
 
-def build_library(verbose: bool = False, jobs: int = 2) -> Path:
+def build_library(verbose: bool = False, jobs: int = 3) -> Path:
     """Compile every HIP source of the library and link libspamm.so."""
     objs = []
     procs = []

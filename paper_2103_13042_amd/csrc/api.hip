@@ -54,7 +54,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
-    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, pairs, total;
+    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix, pairs,
+        total;
 };
 
 Layout make_layout(const Geom& g) {
@@ -74,6 +75,10 @@ Layout make_layout(const Geom& g) {
     L.offsets = take(sizeof(int32_t) * size_t(g.ntiles + 1));
     L.klist = take(sizeof(int32_t) * size_t(g.ntiles) * size_t(g.bdim));
     L.pair_scratch = take(sizeof(int32_t) * size_t(g.ntiles) * size_t(g.bdim));
+    const size_t nm = size_t((g.bdim + 1) / 2) * size_t((g.bdim + 1) / 2);
+    L.mwords = take(sizeof(uint64_t) * nm * 4 * size_t(g.nwords));
+    L.mcount = take(sizeof(int32_t) * nm);
+    L.mprefix = take(sizeof(int32_t) * (nm + 1));
     L.pairs = take(sizeof(int64_t));
     L.total = o;
     return L;
@@ -258,9 +263,16 @@ spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t le
     if ((st = check_grid(g)) != SPAMM_OK) return st;
     if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
     const bool vec = (n % 4) == 0 && aligned16(a) && aligned16(b);
-    int32_t* scratch = at<int32_t>(workspace, make_layout(g).pair_scratch);
-    return hip_check(spamm::launch_multiply(a, b, c, n, leaf, g.bdim, offsets, klist, scratch, vec, device_cus(),
-                                            static_cast<hipStream_t>(stream)),
+    const Layout L = make_layout(g);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (leaf == 32 || leaf == 64)
+        return hip_check(spamm::launch_multiply_macro(a, b, c, n, leaf, g.bdim, offsets, klist,
+                                                      at<uint64_t>(workspace, L.mwords),
+                                                      at<int32_t>(workspace, L.mcount),
+                                                      at<int32_t>(workspace, L.mprefix), vec, device_cus(), s),
+                         "macro multiply kernels");
+    return hip_check(spamm::launch_multiply(a, b, c, n, leaf, g.bdim, offsets, klist,
+                                            at<int32_t>(workspace, L.pair_scratch), vec, device_cus(), s),
                      "multiply kernel");
 }
 

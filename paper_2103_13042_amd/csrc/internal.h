@@ -51,4 +51,11 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
                            const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
                            int num_cus, hipStream_t s);
 
+// Multiply on 2x2 macro tiles (leaf 32 and 64): per-macro-tile k bitmaps into
+// words [mb*mb*4*nwords], union sizes into ucount [mb*mb], their exclusive
+// prefix into uprefix [mb*mb + 1], then the persistent multiply.
+hipError_t launch_multiply_macro(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
+                                 const int32_t* offsets, const int32_t* klist, uint64_t* words, int32_t* ucount,
+                                 int32_t* uprefix, bool vec, int num_cus, hipStream_t s);
+
 }  // namespace spamm

@@ -10,12 +10,10 @@
 // Wave size is 64 throughout.
 #include <hip/hip_runtime.h>
 
+#include "device.h"
 #include "internal.h"
 
 namespace spamm {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef float f16v __attribute__((ext_vector_type(16)));
 
 // --------------------------------------------------------------------------
 // Leaf norms.  A block of 256 threads reads a strip of `leaf` rows by 1024

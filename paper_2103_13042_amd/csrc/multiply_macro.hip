@@ -1,0 +1,581 @@
+// Multiply of the kept leaf pairs on 2x2 blocks of output tiles ("macro
+// tiles"), for leaf 32 and 64.
+//
+// A macro tile (I, J) covers output tiles (2I+a, 2J+b), a, b in {0, 1}.  Its
+// k-stream is the union of the four tiles' k-lists in ascending order; for each
+// k the workgroup stages A[2I..2I+1, k] and B[k, 2J..2J+1] once and every wave
+// (a, b) whose own tile keeps that k multiplies its 64x64 (or 32x32) part.  One
+// staged A/B pair thus feeds up to four leaf products, which halves the bytes
+// per flop against one tile per workgroup for banded pair patterns, and every
+// barrier is amortised over twice the MFMA work.
+//
+// Work units: a persistent grid of G workgroups splits the macro tiles into
+// contiguous row-major ranges of equal cost (kUnionCost per union k plus
+// kMacroWrite per macro tile, from the prefix of union sizes), XCD-aware as in
+// the single-tile kernel.  The k-stream is produced from per-tile bitmaps held
+// in global memory and read with scalar loads; the next two items are always
+// known in registers, so tile prefetch never waits on an index load.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace spamm {
+
+constexpr int kMacThreads = 256;
+constexpr int kUnionCost = 4;
+constexpr int kMacroWrite = 2;
+
+// One wave per macro tile: k-bitmaps of its four tiles (zero for tiles outside
+// the grid) and the size of their union.
+__global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ klist, int64_t bdim, int64_t mb,
+                                                          int nw, uint64_t* __restrict__ words,
+                                                          int32_t* __restrict__ ucount) {
+    __shared__ unsigned long long sw[4][4][16];  // [wave][tile][word]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t m = int64_t(blockIdx.x) * 4 + wave;
+    if (m >= mb * mb) return;
+    const int64_t I = m / mb, J = m - (m / mb) * mb;
+    sw[wave][lane >> 4][lane & 15] = 0ull;
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): zeroing done before the ORs
+    for (int ab = 0; ab < 4; ++ab) {
+        const int64_t ti = 2 * I + (ab >> 1), tj = 2 * J + (ab & 1);
+        if (ti >= bdim || tj >= bdim) continue;
+        const int64_t t = ti * bdim + tj;
+        const int32_t q0 = off[t], q1 = off[t + 1];
+        for (int32_t q = q0 + lane; q < q1; q += 64) {
+            const int32_t k = klist[q];
+            atomicOr(&sw[wave][ab][k >> 6], 1ull << (k & 63));
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    int cnt = 0;
+    if (lane < nw) {
+        const uint64_t u = sw[wave][0][lane] | sw[wave][1][lane] | sw[wave][2][lane] | sw[wave][3][lane];
+        cnt = __popcll(u);
+    }
+    if (lane < 4 * nw) words[(m * 4 + lane / nw) * nw + lane % nw] = sw[wave][lane / nw][lane % nw];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) ucount[m] = cnt;
+}
+
+template <int LEAF>
+struct MacGeom {
+    static constexpr int KC = 32;                 // k per pipeline stage
+    static constexpr int NB = LEAF / 32;          // 32x32 MFMA blocks per wave-tile side
+    static constexpr int SPC = KC / 2;            // MFMA steps per stage (two lane groups)
+    static constexpr int NCH = LEAF / KC;         // stages per leaf pair
+    static constexpr int ROWS = 2 * LEAF;         // A rows / B columns staged per item
+    static constexpr int AST = KC + 4;            // A row stride (floats)
+    static constexpr int BST = ROWS;              // B row stride (floats)
+    static constexpr int ASZ = ROWS * AST;
+    static constexpr int STAGE = ASZ + KC * BST;
+    static constexpr int NV = ROWS * KC / 4 / kMacThreads;  // float4 per thread per operand
+    static constexpr int OCC = LEAF == 64 ? 2 : 4;          // workgroups per CU
+    static_assert(NV >= 1 && NV * 4 * kMacThreads == ROWS * KC, "stage split");
+};
+
+// packed pair item: I << 23 | J << 14 | k << 4 | membership (bit a*2+b)
+__device__ __forceinline__ uint32_t mi_pack(uint32_t I, uint32_t J, uint32_t k, uint32_t mem) {
+    return (I << 23) | (J << 14) | (k << 4) | mem;
+}
+
+template <int LEAF, bool VEC>
+__global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macro_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
+    int64_t mb, int nw, const uint64_t* __restrict__ words, const int32_t* __restrict__ uprefix) {
+    using Gm = MacGeom<LEAF>;
+    __shared__ __attribute__((aligned(16))) float lds[2 * Gm::STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wa = wave >> 1, wb = wave & 1;
+    const int ir = lane & 31, g = lane >> 5;
+
+    // this group's range of macro tiles
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t nm = mb * mb;
+    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
+    auto start_of = [&](int64_t gg) {
+        const int64_t target = gg * total;
+        int64_t lo = 0, hi = nm;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    };
+    const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
+    if (m_begin >= m_end) return;
+    const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]) * Gm::NCH;
+
+    // producer of the union k-stream (wave-uniform state)
+    int64_t pm = m_begin;
+    int pw = -1;
+    uint64_t prem = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    uint32_t last = 0;
+    auto produce = [&]() -> uint32_t {
+        while (prem == 0) {
+            if (++pw == nw) {
+                pw = 0;
+                ++pm;
+            }
+            if (pm >= m_end) return last;  // past the end: repeat the last item (a harmless reload)
+            const uint64_t* wp = words + pm * 4 * nw + pw;
+            w0 = wp[0];
+            w1 = wp[nw];
+            w2 = wp[2 * nw];
+            w3 = wp[3 * nw];
+            prem = w0 | w1 | w2 | w3;
+        }
+        const uint32_t bit = uint32_t(__builtin_ctzll(prem));
+        prem &= prem - 1;
+        const uint32_t mem = uint32_t((w0 >> bit) & 1) | uint32_t(((w1 >> bit) & 1) << 1) |
+                             uint32_t(((w2 >> bit) & 1) << 2) | uint32_t(((w3 >> bit) & 1) << 3);
+        const uint32_t I = uint32_t(pm / mb), J = uint32_t(pm - (pm / mb) * mb);
+        last = mi_pack(I, J, uint32_t(pw) * 64 + bit, mem);
+        return last;
+    };
+
+    typedef f16v acc_t;
+    acc_t acc[Gm::NB][Gm::NB];
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int a = 0; a < Gm::NB; ++a)
+#pragma unroll
+            for (int b = 0; b < Gm::NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    };
+    auto store_macro = [&](int64_t m) {
+        const int64_t ti = 2 * (m / mb) + wa, tj = 2 * (m - (m / mb) * mb) + wb;
+        if (ti >= bdim || tj >= bdim) return;
+#pragma unroll
+        for (int a = 0; a < Gm::NB; ++a)
+#pragma unroll
+            for (int b = 0; b < Gm::NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t row = ti * LEAF + a * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+                    const int64_t col = tj * LEAF + b * 32 + ir;
+                    if (row < n && col < n) C[row * n + col] = acc[a][b][r];
+                }
+    };
+
+    // global -> registers for one item (pair item pi, chunk ch): A rows
+    // [2I*L, 2I*L + 2L) x k-chunk, B k-chunk x columns [2J*L, 2J*L + 2L).  Every
+    // lane issues every load (clamped) and zeroes what lies outside the matrix.
+    auto fetch = [&](uint32_t pi, int ch, f4 (&ra)[Gm::NV], f4 (&rb)[Gm::NV]) {
+        const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
+        const int64_t arow0 = 2 * I * LEAF, acol0 = kt * LEAF + ch * Gm::KC;
+        const int64_t brow0 = kt * LEAF + ch * Gm::KC, bcol0 = 2 * J * LEAF;
+        const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int v = 0; v < Gm::NV; ++v) {
+            const int e = tid + v * kMacThreads;
+            {
+                const int r = e / (Gm::KC / 4), c4 = e % (Gm::KC / 4);
+                const int64_t row = arow0 + r, col = acol0 + 4 * c4;
+                if (VEC) {
+                    const bool in = row < n && col < n;
+                    const f4 x = *reinterpret_cast<const f4*>(A + (in ? row * n + col : 0));
+                    ra[v] = in ? x : zero;
+                } else {
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const bool in = row < n && col + q4 < n;
+                        const float x = A[in ? row * n + col + q4 : 0];
+                        ra[v][q4] = in ? x : 0.0f;
+                    }
+                }
+            }
+            {
+                const int r = e / (Gm::ROWS / 4), c4 = e % (Gm::ROWS / 4);
+                const int64_t row = brow0 + r, col = bcol0 + 4 * c4;
+                if (VEC) {
+                    const bool in = row < n && col < n;
+                    const f4 x = *reinterpret_cast<const f4*>(B + (in ? row * n + col : 0));
+                    rb[v] = in ? x : zero;
+                } else {
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const bool in = row < n && col + q4 < n;
+                        const float x = B[in ? row * n + col + q4 : 0];
+                        rb[v][q4] = in ? x : 0.0f;
+                    }
+                }
+            }
+        }
+    };
+    auto commit = [&](int stage, const f4 (&ra)[Gm::NV], const f4 (&rb)[Gm::NV]) {
+        float* sa = lds + stage * Gm::STAGE;
+        float* sb = sa + Gm::ASZ;
+#pragma unroll
+        for (int v = 0; v < Gm::NV; ++v) {
+            const int e = tid + v * kMacThreads;
+            {
+                const int r = e / (Gm::KC / 4), c4 = e % (Gm::KC / 4);
+                *reinterpret_cast<f4*>(sa + r * Gm::AST + 4 * c4) = ra[v];
+            }
+            {
+                const int r = e / (Gm::ROWS / 4), c4 = e % (Gm::ROWS / 4);
+                const int swz = ((r / Gm::SPC) & 1) * 32;
+                *reinterpret_cast<f4*>(sb + r * Gm::BST + ((4 * c4) ^ swz)) = rb[v];
+            }
+        }
+    };
+    // wave (wa, wb): rows [wa*L, wa*L + L) of the A stage, columns [wb*L, ..) of B.
+    // MFMA step s, lane group g: k = g*SPC + s.
+    auto compute = [&](int stage) {
+        const float* sa = lds + stage * Gm::STAGE + (wa * LEAF + ir) * Gm::AST + g * Gm::SPC;
+        const float* sb = lds + stage * Gm::STAGE + Gm::ASZ + g * Gm::SPC * Gm::BST;
+        const int swz = g * 32;
+#pragma unroll
+        for (int q = 0; q < Gm::SPC / 4; ++q) {
+            f4 av[Gm::NB];
+#pragma unroll
+            for (int a = 0; a < Gm::NB; ++a) av[a] = *reinterpret_cast<const f4*>(sa + a * 32 * Gm::AST + 4 * q);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int s = 4 * q + u;
+                float bv[Gm::NB];
+#pragma unroll
+                for (int b = 0; b < Gm::NB; ++b) bv[b] = sb[s * Gm::BST + ((wb * LEAF + b * 32 + ir) ^ swz)];
+#pragma unroll
+                for (int a = 0; a < Gm::NB; ++a)
+#pragma unroll
+                    for (int b = 0; b < Gm::NB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a][u], bv[b], acc[a][b], 0, 0, 0);
+            }
+        }
+    };
+
+    // pair items of the compute item (f0) and the next two pairs
+    uint32_t f0 = produce();
+    uint32_t f1 = produce();
+    uint32_t f2 = produce();
+    constexpr int AHEAD = 2 / Gm::NCH;  // pair distance of item it+2 from item it's pair
+    int64_t out_m = m_begin;            // macro tile being accumulated; earlier ones are written
+    f4 ra0[Gm::NV], rb0[Gm::NV], ra1[Gm::NV], rb1[Gm::NV];
+    auto step = [&](int64_t it, f4 (&fa)[Gm::NV], f4 (&fb)[Gm::NV], const f4 (&na)[Gm::NV],
+                    const f4 (&nb)[Gm::NV]) {
+        const uint32_t pi = f0;
+        const int64_t m_it = int64_t(pi >> 23) * mb + ((pi >> 14) & 511);
+        while (out_m < m_it) {  // macro tile out_m is complete (or has no pairs)
+            store_macro(out_m);
+            zero_acc();
+            ++out_m;
+        }
+        fetch(AHEAD == 1 ? f1 : f2, int((it + 2) % Gm::NCH), fa, fb);
+        __syncthreads();
+        if ((pi >> wave) & 1) compute(int(it & 1));
+        if (it + 1 < nitems) commit(int((it + 1) & 1), na, nb);
+        if ((it + 1) % Gm::NCH == 0) {
+            f0 = f1;
+            f1 = f2;
+            f2 = produce();
+        }
+    };
+    zero_acc();
+    if (nitems > 0) {
+        fetch(f0, 0, ra0, rb0);
+        if (Gm::NCH == 1)
+            fetch(f1, 0, ra1, rb1);
+        else
+            fetch(f0, 1, ra1, rb1);
+        commit(0, ra0, rb0);
+    }
+    for (int64_t it = 0; it < nitems; it += 2) {
+        step(it, ra0, rb0, ra1, rb1);
+        if (it + 1 >= nitems) break;
+        step(it + 1, ra1, rb1, ra0, rb0);
+    }
+    while (out_m < m_end) {
+        store_macro(out_m);
+        zero_acc();
+        ++out_m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf 64 with N a multiple of 128 (whole macro tiles, every access inside
+// the matrix): the same macro-tile stream, but tiles move from global memory
+// straight into LDS (global_load_lds_dwordx4) through four LDS stages, so three
+// items are in flight while one is multiplied and no registers stage the data.
+//
+// Sixteen waves: wave w computes the 32x32 quadrant (w >> 1 & 1, w & 1) of
+// output tile w >> 2 of the macro tile.  Waves are dealt to the four SIMDs
+// round-robin, so each output tile has one wave on every SIMD and the MFMA
+// load of an item is the same on all SIMDs whichever of the four tiles keep
+// its k.
+//
+// LDS rows are stored without padding; 16-byte chunks are XOR-swizzled so the
+// MFMA operand reads are free of bank conflicts: A row r keeps global chunk c
+// at position c ^ ((r >> 1) & 7), B row r at position c ^ (8 * ((r >> 4) & 1)).
+//
+// Completion of the copies is tracked by hand with s_waitcnt vmcnt: every
+// wave issues exactly 2 copies per item and exactly 16 stores per finished
+// output quadrant (no access is predicated), so the number of memory
+// operations issued after the copies of item it is known.  Empty asm
+// statements with a memory clobber keep the compiler from moving LDS or
+// global accesses across the hand-placed waits and the barrier.
+constexpr int kDmaThreads = 1024;
+constexpr int kDmaStores = 16;  // per wave per macro tile
+#ifndef SPAMM_DMA_KC
+#define SPAMM_DMA_KC 32
+#endif
+#ifndef SPAMM_DMA_STAGES
+#define SPAMM_DMA_STAGES 4
+#endif
+constexpr int kDmaKC = SPAMM_DMA_KC;          // k per item
+constexpr int kDmaStages = SPAMM_DMA_STAGES;  // LDS stages (items in flight + 1)
+constexpr int kDmaCopies = 2 * kDmaKC / 32;   // copies per wave per item
+static_assert(kDmaStages * (2 * 64 * kDmaKC * 4 * 2) <= 160 * 1024, "LDS budget");
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14));
+}
+
+// wait until at most `newer` vector memory operations are outstanding, where
+// newer = BASE + kDmaStores * stores (above 63: wait for 63, which forces the
+// awaited copies too because operations complete in issue order)
+template <int BASE>
+__device__ __forceinline__ void wait_copies(int stores) {
+    switch (stores) {
+        case 0: wait_vmcnt<BASE>(); break;
+        case 1: wait_vmcnt<(BASE + kDmaStores > 63 ? 63 : BASE + kDmaStores)>(); break;
+        case 2: wait_vmcnt<(BASE + 2 * kDmaStores > 63 ? 63 : BASE + 2 * kDmaStores)>(); break;
+        case 3: wait_vmcnt<(BASE + 3 * kDmaStores > 63 ? 63 : BASE + 3 * kDmaStores)>(); break;
+        default: wait_vmcnt<63>(); break;
+    }
+}
+
+__global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
+    int64_t mb, int nw, const uint64_t* __restrict__ words, const int32_t* __restrict__ uprefix) {
+    constexpr int LEAF = 64, KC = kDmaKC, NCH = LEAF / KC, SPC = KC / 2;
+    constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;  // 16 KiB each
+    constexpr int STAGE_BYTES = ABYTES + BBYTES;
+    __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = wave >> 2, wa = tile >> 1, wb = tile & 1, qr = (wave >> 1) & 1, qc = wave & 1;
+    const int ir = lane & 31, g = lane >> 5;
+
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t nm = mb * mb;
+    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
+    auto start_of = [&](int64_t gg) {
+        const int64_t target = gg * total;
+        int64_t lo = 0, hi = nm;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    };
+    const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
+    if (m_begin >= m_end) return;
+    const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]) * NCH;
+
+    int64_t pm = m_begin;
+    int pw = -1;
+    uint64_t prem = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    uint32_t last = 0;
+    auto produce = [&]() -> uint32_t {
+        while (prem == 0) {
+            if (++pw == nw) {
+                pw = 0;
+                ++pm;
+            }
+            if (pm >= m_end) return last;
+            const uint64_t* wp = words + pm * 4 * nw + pw;
+            w0 = wp[0];
+            w1 = wp[nw];
+            w2 = wp[2 * nw];
+            w3 = wp[3 * nw];
+            prem = w0 | w1 | w2 | w3;
+        }
+        const uint32_t bit = uint32_t(__builtin_ctzll(prem));
+        prem &= prem - 1;
+        const uint32_t mem = uint32_t((w0 >> bit) & 1) | uint32_t(((w1 >> bit) & 1) << 1) |
+                             uint32_t(((w2 >> bit) & 1) << 2) | uint32_t(((w3 >> bit) & 1) << 3);
+        const uint32_t I = uint32_t(pm / mb), J = uint32_t(pm - (pm / mb) * mb);
+        last = mi_pack(I, J, uint32_t(pw) * 64 + bit, mem);
+        return last;
+    };
+
+    f16v acc;
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    };
+    // exactly kDmaStores stores per wave
+    auto store_macro = [&](int64_t m) {
+        const int64_t ti = 2 * (m / mb) + wa, tj = 2 * (m - (m / mb) * mb) + wb;
+        float* dst = C + (ti * LEAF + qr * 32 + 4 * g) * n + tj * LEAF + qc * 32 + ir;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[(8 * (r >> 2) + (r & 3)) * n] = acc[r];
+    };
+
+    // copies of item (pair item pi, chunk ch) into stage st: KC/32 A and KC/32
+    // B instructions of 1 KiB per wave
+    constexpr int ACH = KC / 4;  // 16-byte chunks per A row
+    auto aswz = [](int r) { return KC == 32 ? ((r >> 1) & 7) : (r & 15); };
+    auto copy_item = [&](uint32_t pi, int ch, int st) {
+        const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
+        char* sbase = lds + st * STAGE_BYTES;
+#pragma unroll
+        for (int j = 0; j < KC / 32; ++j) {  // A: 1024 / (4 KC) rows per instruction
+            const int blk = wave * (KC / 32) + j;
+            const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
+            const int c = p ^ aswz(r);
+            const float* src = A + (2 * I * LEAF + r) * n + kt * LEAF + ch * KC + 4 * c;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sbase + blk * 1024), 16, 0,
+                                             0);
+        }
+#pragma unroll
+        for (int j = 0; j < KC / 32; ++j) {  // B: 2 rows of 32 chunks per instruction
+            const int blk = wave * (KC / 32) + j;
+            const int r = blk * 2 + (lane >> 5), p = lane & 31;
+            const int c = p ^ (8 * ((r / SPC) & 1));
+            const float* src = B + (kt * LEAF + ch * KC + r) * n + 2 * J * LEAF + 4 * c;
+            __builtin_amdgcn_global_load_lds(src,
+                                             (__attribute__((address_space(3))) void*)(sbase + ABYTES + blk * 1024),
+                                             16, 0, 0);
+        }
+    };
+    auto compute = [&](int st) {
+        const char* sa = lds + st * STAGE_BYTES;
+        const char* sb = sa + ABYTES;
+        const int r = wa * 64 + qr * 32 + ir;
+        const int cc = wb * 64 + qc * 32 + ir;
+        const char* brow = sb + ((cc >> 2) ^ (8 * g)) * 16 + (cc & 3) * 4;
+#pragma unroll
+        for (int q = 0; q < SPC / 4; ++q) {
+            const int c = (g * (SPC / 4) + q) ^ aswz(r);
+            const f4 av = *reinterpret_cast<const f4*>(sa + r * (KC * 4) + c * 16);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kr = g * SPC + 4 * q + u;
+                const float bv = *reinterpret_cast<const float*>(brow + kr * (2 * LEAF * 4));
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, acc, 0, 0, 0);
+            }
+        }
+    };
+
+    // pair items of item it (f[0]) and of the next pairs; item it + S - 1 lies
+    // at most S - 1 pairs ahead
+    constexpr int S = kDmaStages;
+    uint32_t f[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) f[i] = produce();
+#pragma unroll
+    for (int i = 0; i < S - 1; ++i) copy_item(f[i / NCH], i % NCH, i);
+    int64_t out_m = m_begin;
+    int ns[S];  // macro tiles stored in the last S-1 steps (ns[0]: this step)
+#pragma unroll
+    for (int i = 0; i < S; ++i) ns[i] = 0;
+    zero_acc();
+    for (int64_t it = 0; it < nitems; ++it) {
+        const uint32_t pi = f[0];
+        const int64_t m_it = int64_t(pi >> 23) * mb + ((pi >> 14) & 511);
+#pragma unroll
+        for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
+        ns[0] = 0;
+        while (out_m < m_it) {
+            store_macro(out_m);
+            zero_acc();
+            ++out_m;
+            ++ns[0];
+        }
+        int stores = 0;
+#pragma unroll
+        for (int i = 0; i < S - 1; ++i) stores += ns[i];
+        // this wave's copies of item it are complete once at most the copies
+        // of items it+1 .. it+S-2 and the stores issued since are outstanding
+        asm volatile("" ::: "memory");
+        wait_copies<(S - 2) * kDmaCopies>(stores);
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS reads of item it-1 are done
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        {   // item it+S-1 -> the stage item it-1 used
+            const int64_t il = it + S - 1;
+            const int ahead = int((it % NCH + S - 1) / NCH);  // pairs ahead of item it's pair
+            uint32_t pl = f[0];
+#pragma unroll
+            for (int i = 1; i < S; ++i)
+                if (ahead == i) pl = f[i];
+            copy_item(pl, int(il % NCH), int(il % S));
+        }
+        if ((pi >> tile) & 1) compute(int(it % S));
+        if ((it + 1) % NCH == 0) {
+#pragma unroll
+            for (int i = 0; i < S - 1; ++i) f[i] = f[i + 1];
+            f[S - 1] = produce();
+        }
+    }
+    int64_t m_last = out_m;
+    while (m_last < m_end) {
+        store_macro(m_last);
+        zero_acc();
+        ++m_last;
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
+}
+
+template <int LEAF>
+static hipError_t launch_macro(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                               const int32_t* offsets, const int32_t* klist, uint64_t* words, int32_t* ucount,
+                               int32_t* uprefix, bool vec, int num_cus, hipStream_t s) {
+    const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
+    const int nw = int((bdim + 63) / 64);
+    macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, words, ucount);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_plan_scan(ucount, nm, uprefix, uprefix, nm, nullptr, s);
+    if (e != hipSuccess) return e;
+    const int64_t cap = ((nm + 7) / 8) * 8;
+    if (LEAF == 64 && vec && n % 128 == 0) {
+        int64_t groups = int64_t(num_cus);
+        if (groups > cap) groups = cap;
+        groups = ((groups + 7) / 8) * 8;
+        multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, bdim, mb, nw, words, uprefix);
+        return hipGetLastError();
+    }
+    int64_t groups = int64_t(num_cus) * MacGeom<LEAF>::OCC;
+    if (groups > cap) groups = cap;
+    groups = ((groups + 7) / 8) * 8;
+    if (vec)
+        multiply_macro_kernel<LEAF, true>
+            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, nw, words, uprefix);
+    else
+        multiply_macro_kernel<LEAF, false>
+            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, nw, words, uprefix);
+    return hipGetLastError();
+}
+
+hipError_t launch_multiply_macro(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
+                                 const int32_t* offsets, const int32_t* klist, uint64_t* words, int32_t* ucount,
+                                 int32_t* uprefix, bool vec, int num_cus, hipStream_t s) {
+    switch (leaf) {
+        case 32: return launch_macro<32>(a, b, c, n, bdim, offsets, klist, words, ucount, uprefix, vec, num_cus, s);
+        case 64: return launch_macro<64>(a, b, c, n, bdim, offsets, klist, words, ucount, uprefix, vec, num_cus, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace spamm
