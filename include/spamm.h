@@ -134,6 +134,24 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
 spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,
                             int64_t* pairs, void* workspace, size_t workspace_bytes, void* stream);
 
+/* The valid-ratio search of section 3.5.2: the threshold tau whose valid
+ * ratio (kept leaf triples / bdim^3) is within tol of target.  ave is the
+ * mean of the norm products over all bdim^3 triples; tau starts at ave; while
+ * the ratio at the upper bound k*ave exceeds target + tol, k grows by one (at
+ * most 1024 times); then tau is bisected in [0, k*ave] until the ratio is
+ * within tol of target or max_iters bisections ran.
+ *   pyr_a, pyr_b  pyramids from spamm_pyramid (device).
+ *   tau_out       HOST double: the threshold found (the last one tried).
+ *   pairs_out     HOST int64 (may be NULL): kept triples at tau_out.
+ *   iters_out     HOST int32 (may be NULL): bisection steps taken.
+ * Synchronous: reads each count back to the host (the stream is synchronised
+ * once per tried tau).  EINVAL: target outside (0, 1], tol < 0,
+ * max_iters < 0, null pointer. */
+spamm_status spamm_search_valid_ratio(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf,
+                                      double target, double tol, int32_t max_iters, double* tau_out,
+                                      int64_t* pairs_out, int32_t* iters_out, void* workspace, size_t workspace_bytes,
+                                      void* stream);
+
 /* Static description of a status code. */
 const char* spamm_strerror(spamm_status status);
 

@@ -171,3 +171,57 @@ def tiles_to_matrix_view(ctiles: np.ndarray, tiles: np.ndarray, n: int, leaf: in
 def threads_env() -> int:
     v = os.environ.get("OMP_NUM_THREADS")
     return int(v) if v and v.isdigit() else max_threads()
+
+
+def mean_norm_product(a, b, leaf: int) -> float:
+    """Mean of nA[i,k] * nB[k,j] over every leaf triple (i, k, j) of the real
+    bdim^3 grid: the `ave` of the valid-ratio search (section 3.5.2)."""
+    na, nb = leaf_norms(a, leaf), leaf_norms(b, leaf)
+    prods = na[:, :, None] * nb[None, :, :]  # [i, k, j]
+    return float(prods.sum() / prods.size)
+
+
+def valid_ratio(a, b, tau: float, leaf: int, *, pyr_a=None, pyr_b=None) -> tuple[float, int]:
+    """Fraction of leaf triples multiplied at tau, and their number (section 3.5.2)."""
+    a = _as_f32(a)
+    n = a.shape[0]
+    bd = bdim(n, leaf)
+    _, counts, _ = spamm_tiles(a, b, tau, leaf, all_tiles(n, leaf), products=False, pyr_a=pyr_a, pyr_b=pyr_b)
+    c = int(counts.sum())
+    return c / bd**3, c
+
+
+def search_tau_for_valid_ratio(a, b, leaf: int, target: float, tol: float = 0.01, max_iters: int = 20,
+                               max_expand: int = 1024):
+    """The valid-ratio search of section 3.5.2: the first tau tried is ave (the
+    mean norm product); while the ratio at the upper bound k*ave is still above
+    the target (plus tol), k grows to k+1 (at most max_expand); then tau is
+    bisected in [0, k*ave] until the ratio is within tol of the target or
+    max_iters bisections ran.
+    Returns (tau, pairs, bisections)."""
+    pa, pb = pyramid(a, leaf), pyramid(b, leaf)
+    ave = mean_norm_product(a, b, leaf)
+
+    def ratio(t):
+        return valid_ratio(a, b, t, leaf, pyr_a=pa, pyr_b=pb)
+
+    k = 1
+    hi = k * ave
+    r, cnt = ratio(hi)
+    while r > target + tol and k < max_expand:
+        k += 1
+        hi = k * ave
+        r, cnt = ratio(hi)
+    tau = hi
+    lo = 0.0
+    it = 0
+    while abs(r - target) > tol and it < max_iters:
+        mid = 0.5 * (lo + hi)
+        r, cnt = ratio(mid)
+        tau = mid
+        it += 1
+        if r > target:
+            lo = mid
+        else:
+            hi = mid
+    return tau, cnt, it

@@ -11,7 +11,7 @@ from __future__ import annotations
 __all__ = [
     "bdim", "levels", "pyramid_size", "leaf_supported", "workspace_bytes", "workspace",
     "norms", "pyramid", "pyramid_levels", "plan", "plan_buffers", "prepare", "execute", "multiply",
-    "SpammError",
+    "search_valid_ratio", "SpammError",
 ]
 
 

@@ -37,6 +37,7 @@ _SIGS = {
     "spamm_execute": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "spamm_multiply": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_search_valid_ratio": (_st, [_vp, _vp, _i64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_strerror": (ctypes.c_char_p, [_st]),
     "spamm_last_error": (ctypes.c_char_p, []),
 }
@@ -234,3 +235,25 @@ def multiply(a, b, tau: float, leaf: int, *, c=None, pairs=None, ws=None, sync: 
         "spamm_multiply",
     )
     return (c, int(pairs.item())) if sync else (c, pairs)
+
+
+def search_valid_ratio(pyr_a, pyr_b, n: int, leaf: int, target: float, tol: float = 0.01, max_iters: int = 20,
+                       *, ws=None):
+    """tau for a requested valid ratio (spamm_search_valid_ratio): (tau, pairs, bisections)."""
+    dev = pyr_a.device
+    size = pyramid_size(n, leaf)
+    for name, p in (("pyr_a", pyr_a), ("pyr_b", pyr_b)):
+        if p.dtype != torch.float64 or not p.is_cuda or not p.is_contiguous() or p.numel() != size:
+            raise ValueError(f"{name}: expected a contiguous CUDA float64 pyramid of {size} entries")
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    tau = ctypes.c_double(0.0)
+    pairs = ctypes.c_int64(0)
+    iters = ctypes.c_int32(0)
+    _check(
+        _lib.spamm_search_valid_ratio(
+            _ptr(pyr_a), _ptr(pyr_b), n, leaf, float(target), float(tol), int(max_iters), ctypes.byref(tau),
+            ctypes.byref(pairs), ctypes.byref(iters), _ptr(ws), ws.numel(), _stream(dev),
+        ),
+        "spamm_search_valid_ratio",
+    )
+    return tau.value, pairs.value, iters.value

@@ -55,7 +55,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
     size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix, pairs,
-        total;
+        scalars, total;
 };
 
 Layout make_layout(const Geom& g) {
@@ -80,6 +80,7 @@ Layout make_layout(const Geom& g) {
     L.mcount = take(sizeof(int32_t) * nm);
     L.mprefix = take(sizeof(int32_t) * (nm + 1));
     L.pairs = take(sizeof(int64_t));
+    L.scalars = take(2 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -318,6 +319,77 @@ spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double ta
                        stream);
     if (st != SPAMM_OK) return st;
     return spamm_execute(a, b, n, leaf, offsets, klist, c, workspace, workspace_bytes, stream);
+}
+
+spamm_status spamm_search_valid_ratio(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf,
+                                      double target, double tol, int32_t max_iters, double* tau_out,
+                                      int64_t* pairs_out, int32_t* iters_out, void* workspace, size_t workspace_bytes,
+                                      void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!pyr_a || !pyr_b || !tau_out) return fail(SPAMM_EINVAL, "null pointer");
+    if (!(target > 0.0 && target <= 1.0)) return fail(SPAMM_EINVAL, "target valid ratio must be in (0, 1]");
+    if (!(tol >= 0.0) || max_iters < 0) return fail(SPAMM_EINVAL, "tol must be >= 0 and max_iters >= 0");
+    spamm_status st = check_grid(g);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = make_layout(g);
+    double* d_ave = at<double>(workspace, L.scalars);
+    int32_t* bsums = at<int32_t>(workspace, L.bsums);
+    int64_t* d_pairs = at<int64_t>(workspace, L.pairs);
+    const int64_t nb = g.bdim * g.nwords;
+    const double triples = double(g.bdim) * double(g.bdim) * double(g.bdim);
+
+    if ((st = hip_check(spamm::launch_mean_norm_product(pyr_a, pyr_b, g.bdim, g.lv, d_ave, s), "mean kernel")) !=
+        SPAMM_OK)
+        return st;
+    double ave = 0.0;
+    if ((st = hip_check(hipMemcpyAsync(&ave, d_ave, sizeof(double), hipMemcpyDeviceToHost, s), "copy")) != SPAMM_OK)
+        return st;
+    if ((st = hip_check(hipStreamSynchronize(s), "synchronize")) != SPAMM_OK) return st;
+
+    int64_t cnt = 0;
+    auto ratio = [&](double t, double* r) -> spamm_status {
+        spamm_status e = hip_check(spamm::launch_plan_count(pyr_a, pyr_b, g.bdim, g.lv, t, bsums, s), "count kernel");
+        if (e != SPAMM_OK) return e;
+        e = hip_check(spamm::launch_plan_scan(bsums, nb, nullptr, nullptr, nb, d_pairs, s), "scan kernel");
+        if (e != SPAMM_OK) return e;
+        e = hip_check(hipMemcpyAsync(&cnt, d_pairs, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+        if (e != SPAMM_OK) return e;
+        e = hip_check(hipStreamSynchronize(s), "synchronize");
+        *r = double(cnt) / triples;
+        return e;
+    };
+    // section 3.5.2: tau starts at ave; the upper bound k*ave grows by ave
+    // while the ratio there is still above the target; then bisection in
+    // [0, k*ave] until the ratio is within tol or max_iters bisections ran
+    constexpr int kMaxExpand = 1024;
+    int k = 1;
+    double hi = ave, r = 0.0;
+    if ((st = ratio(hi, &r)) != SPAMM_OK) return st;
+    while (r > target + tol && k < kMaxExpand) {
+        ++k;
+        hi = k * ave;
+        if ((st = ratio(hi, &r)) != SPAMM_OK) return st;
+    }
+    double tau = hi, lo = 0.0;
+    int it = 0;
+    while (std::fabs(r - target) > tol && it < max_iters) {
+        const double mid = 0.5 * (lo + hi);
+        if ((st = ratio(mid, &r)) != SPAMM_OK) return st;
+        tau = mid;
+        ++it;
+        if (r > target)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *tau_out = tau;
+    if (pairs_out) *pairs_out = cnt;
+    if (iters_out) *iters_out = it;
+    return SPAMM_OK;
 }
 
 const char* spamm_strerror(spamm_status status) {

@@ -37,7 +37,15 @@ hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv,
 // count V; per block of 64 tiles (i, 64*jb ..) the sum of V (block b = i*nw + jb).
 hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
                             uint64_t* masks, int32_t* counts, int32_t* block_sums, hipStream_t s);
-// Plan: exclusive scan of the block sums; the total goes to offsets[T] and *pairs.
+// Plan counts only (no bitmaps): per block of 64 tiles the number of kept triples.
+hipError_t launch_plan_count(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+                             int32_t* block_sums, hipStream_t s);
+// Mean norm product over the bdim^3 leaf triples, into one device double.
+hipError_t launch_mean_norm_product(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double* out,
+                                    hipStream_t s);
+// Plan: exclusive scan of the block sums into block_offsets; the total goes to
+// offsets[T] and *pairs.  Each of the three outputs may be null; block_offsets
+// and offsets may be the same array (they are written at disjoint indices).
 hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t* block_offsets, int32_t* offsets,
                             int64_t ntiles, int64_t* pairs, hipStream_t s);
 // Plan: per tile offset (block offset + prefix inside the block) and the

@@ -188,6 +188,7 @@ hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv,
 
 constexpr int kPlanThreads = 256;
 
+template <bool MASKS>
 __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* __restrict__ pyr_a,
                                                                  const double* __restrict__ pyr_b, int64_t bdim,
                                                                  int lv, double tau, uint64_t* __restrict__ masks,
@@ -215,10 +216,12 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
             keep = pyr_a[0] * pyr_b[0] >= tau;
         }
         if (!keep) {
+            if (MASKS) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int64_t j = j0 + wave + 4 * u;
-                if (lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = 0ull;
+                for (int u = 0; u < 16; ++u) {
+                    const int64_t j = j0 + wave + 4 * u;
+                    if (lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = 0ull;
+                }
             }
             continue;
         }
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
             const double p = a * sb[lane][jj];
             const bool bit = (p >= tau) && (k < bdim) && (j < bdim);
             const uint64_t mk = __ballot(bit);
-            if (lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = mk;
+            if (MASKS && lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = mk;
             cnt[u] += __popcll(mk);
         }
     }
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
     for (int u = 0; u < 16; ++u) {
         const int64_t j = j0 + wave + 4 * u;
         if (j < bdim) {
-            if (lane == 0) counts[i * bdim + j] = cnt[u];
+            if (MASKS && lane == 0) counts[i * bdim + j] = cnt[u];
             tot += cnt[u];
         }
     }
@@ -267,7 +270,48 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
 hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
                             uint64_t* masks, int32_t* counts, int32_t* block_sums, hipStream_t s) {
     dim3 grid{unsigned((bdim + 63) / 64), unsigned(bdim), 1u};
-    plan_mask_kernel<<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts, block_sums);
+    plan_mask_kernel<true><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts, block_sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_count(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+                             int32_t* block_sums, hipStream_t s) {
+    dim3 grid{unsigned((bdim + 63) / 64), unsigned(bdim), 1u};
+    plan_mask_kernel<false><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, nullptr, nullptr, block_sums);
+    return hipGetLastError();
+}
+
+// Mean of nA[i,k] * nB[k,j] over all leaf triples of the bdim^3 grid, as
+// sum_k (sum_i nA[i,k]) (sum_j nB[k,j]) / bdim^3 (one block; FP64; fixed order).
+constexpr int kAveThreads = 1024;
+
+__global__ __launch_bounds__(kAveThreads) void mean_norm_product_kernel(const double* __restrict__ pyr_a,
+                                                                        const double* __restrict__ pyr_b,
+                                                                        int64_t bdim, int lv, double* __restrict__ out) {
+    __shared__ double wsum[kAveThreads / 64];
+    const int64_t side = int64_t(1) << lv;
+    const double* la = pyr_a + level_offset(lv);
+    const double* lb = pyr_b + level_offset(lv);
+    double part = 0.0;
+    for (int64_t k = threadIdx.x; k < bdim; k += kAveThreads) {
+        double ca = 0.0, rb = 0.0;
+        for (int64_t i = 0; i < bdim; ++i) ca += la[i * side + k];
+        for (int64_t j = 0; j < bdim; ++j) rb += lb[k * side + j];
+        part += ca * rb;
+    }
+    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kAveThreads / 64; ++w) tot += wsum[w];
+        *out = tot / (double(bdim) * double(bdim) * double(bdim));
+    }
+}
+
+hipError_t launch_mean_norm_product(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double* out,
+                                    hipStream_t s) {
+    mean_norm_product_kernel<<<1, kAveThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, out);
     return hipGetLastError();
 }
 
@@ -276,8 +320,8 @@ hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bd
 constexpr int kScanThreads = 256;
 
 __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* __restrict__ block_sums,
-                                                                 int64_t nb, int32_t* __restrict__ block_offsets,
-                                                                 int32_t* __restrict__ offsets, int64_t nt,
+                                                                 int64_t nb, int32_t* block_offsets,
+                                                                 int32_t* offsets, int64_t nt,
                                                                  int64_t* __restrict__ pairs) {
     __shared__ int64_t wsum[kScanThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -295,14 +339,16 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* 
     __syncthreads();
     int64_t run = incl - local;
     for (int w = 0; w < wave; ++w) run += wsum[w];
-    for (int64_t t = b; t < e; ++t) {
-        block_offsets[t] = int32_t(run);
-        run += block_sums[t];
+    if (block_offsets) {
+        for (int64_t t = b; t < e; ++t) {
+            block_offsets[t] = int32_t(run);
+            run += block_sums[t];
+        }
     }
     if (tid == kScanThreads - 1) {
         int64_t total = 0;
         for (int w = 0; w < kScanThreads / 64; ++w) total += wsum[w];
-        offsets[nt] = int32_t(total);
+        if (offsets) offsets[nt] = int32_t(total);
         if (pairs) *pairs = total;
     }
 }

@@ -75,9 +75,26 @@ def algebraic_decay_signed(n: int, seed: int, power: float = 2.0) -> np.ndarray:
     return _build(n, lambda r, c, d: sign_pm1(seed, r, c) / (1.0 + d) ** power)
 
 
+def paper_algebraic_band(n: int) -> np.ndarray:
+    """v[d] = 0.1 / (d^0.1 + 1) for d = 0 .. n-1, rounded to float32: the
+    distinct entries of the paper's synthetic matrix (section 4.1)."""
+    d = np.arange(max(n, 0), dtype=np.float64)
+    return (0.1 / (d ** 0.1 + 1.0)).astype(np.float32)
+
+
 def paper_algebraic(n: int) -> np.ndarray:
-    """The paper's synthetic evaluation matrix, a_ij = 0.1 / (|i-j|^0.1 + 1) (section 4.1)."""
-    return _build(n, lambda r, c, d: 0.1 / (d ** 0.1 + 1.0))
+    """The paper's synthetic evaluation matrix, a_ij = 0.1 / (|i-j|^0.1 + 1) (section 4.1),
+    as the symmetric Toeplitz matrix of paper_algebraic_band(n)."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    v = paper_algebraic_band(n)
+    out = np.empty((n, n), dtype=np.float32)
+    cols = np.arange(n, dtype=np.int64)[None, :]
+    for r0 in range(0, n, _ROWS_PER_CHUNK):
+        r1 = min(n, r0 + _ROWS_PER_CHUNK)
+        rows = np.arange(r0, r1, dtype=np.int64)[:, None]
+        out[r0:r1] = v[np.abs(rows - cols)]
+    return out
 
 
 def uniform_pm1(n: int, seed: int) -> np.ndarray:

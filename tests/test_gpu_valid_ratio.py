@@ -1,0 +1,103 @@
+"""Valid-ratio search (section 3.5.2) on the GPU, through the C ABI.
+
+The GPU search takes the oracle's steps (mean norm product, upper bound grown
+in steps of the mean, bisection) with counts from the plan kernels; it must
+return the oracle's tau (relative 1e-12: only the summation order of the mean
+differs), the same number of kept triples and the same number of bisections.
+At the sizes the oracle is slow for, it must reproduce the tau Table 1 prints.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_13042_amd import binding as sp
+from paper_2103_13042_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def gpu(x: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def toeplitz_on_device(n: int) -> torch.Tensor:
+    """paper_algebraic(n) built on the device from the same float32 band, so the
+    entries are bitwise those of the host generator without an N^2 host copy."""
+    v = torch.from_numpy(inputs.paper_algebraic_band(n)).to(DEV)
+    w = torch.cat([v.flip(0), v[1:]])  # w[m] = v[|m - (n-1)|]
+    # y[i, j'] = w[i + j'];  x[i, j] = y[i, n-1-j] = w[i - j + n - 1] = v[|i - j|]
+    return torch.as_strided(w, (n, n), (1, 1)).flip(1).contiguous()
+
+
+def test_device_toeplitz_matches_host_generator():
+    n = 777
+    assert torch.equal(toeplitz_on_device(n).cpu(), torch.from_numpy(inputs.paper_algebraic(n)))
+
+
+@pytest.mark.parametrize(
+    "n,leaf,kind,target",
+    [
+        (1024, 32, "paper", 0.30),
+        (2048, 32, "paper", 0.05),
+        (1000, 32, "exp", 0.20),
+        (1100, 64, "alg", 0.10),
+        (300, 32, "exp", 0.50),
+        (4096, 128, "alg", 0.02),
+    ],
+)
+def test_search_matches_oracle(n, leaf, kind, target):
+    if kind == "paper":
+        a = b = inputs.paper_algebraic(n)
+    elif kind == "exp":
+        a, b = inputs.exp_decay(n, 0.05, 40), inputs.exp_decay(n, 0.05, 41)
+    else:
+        a, b = inputs.algebraic_decay_signed(n, 42), inputs.algebraic_decay_signed(n, 43)
+    tau_o, cnt_o, it_o = oracle.search_tau_for_valid_ratio(a, b, leaf, target, 0.01, 20)
+    pa, pb = sp.pyramid(gpu(a), leaf), sp.pyramid(gpu(b), leaf)
+    tau, cnt, it = sp.search_valid_ratio(pa, pb, n, leaf, target, 0.01, 20)
+    assert tau == pytest.approx(tau_o, rel=1e-12, abs=0.0)
+    assert (cnt, it) == (cnt_o, it_o)
+    # the count reported is the plan's count at that tau
+    _, _, pairs = sp.plan(pa, pb, n, leaf, tau)
+    assert int(pairs.item()) == cnt
+
+
+def test_search_zero_matrix_and_bad_arguments():
+    n, leaf = 256, 32
+    z = torch.zeros(n, n, dtype=torch.float32, device=DEV)
+    pz = sp.pyramid(z, leaf)
+    # every product is 0 and the mean is 0: tau stays 0 and every triple is kept
+    tau, cnt, it = sp.search_valid_ratio(pz, pz, n, leaf, 0.5, 0.01, 5)
+    assert tau == 0.0 and cnt == (n // leaf) ** 3 and it == 5
+    for target in (0.0, -0.1, 1.5, float("nan")):
+        with pytest.raises(sp.SpammError):
+            sp.search_valid_ratio(pz, pz, n, leaf, target)
+    with pytest.raises(sp.SpammError):
+        sp.search_valid_ratio(pz, pz, n, leaf, 0.5, -1.0)
+    with pytest.raises(ValueError):
+        sp.search_valid_ratio(pz[:-1], pz[:-1], n, leaf, 0.5)
+
+
+def _golden_rows(golden, n):
+    return [(t, tau) for t, nn, tau in golden("table1_tau.txt") if int(nn) == n]
+
+
+@pytest.mark.parametrize("n", [8192, 16384, 32768])
+def test_search_reproduces_table1(golden, n):
+    leaf = 32
+    x = toeplitz_on_device(n)
+    p = sp.pyramid(x, leaf)
+    del x
+    torch.cuda.synchronize()
+    bd = n // leaf
+    for target, tau_paper in _golden_rows(golden, n):
+        tau, cnt, it = sp.search_valid_ratio(p, p, n, leaf, target / 100.0, 0.01, 20)
+        assert abs(tau - tau_paper) <= 1.5e-6, (n, target, tau, tau_paper)
+        assert abs(cnt / bd**3 - target / 100.0) <= 0.01
+        assert 1 <= it < 20

@@ -372,6 +372,42 @@ def _check_table1(golden, sizes):
             assert abs(ratio - target) <= 1.0, (n, target, tau, ratio)
 
 
+def test_valid_ratio_search_reproduces_table1_tau(golden):
+    # Table 1 prints the tau that the valid-ratio search of section 3.5.2
+    # returns.  The search (start at the mean norm product, grow the upper
+    # bound in steps of it, then bisect, 1 % tolerance) must land on the same
+    # tau to the six decimals printed: this pins the mean, the expansion and
+    # the bisection order, not only the tie rule.
+    rows = golden("table1_tau.txt")
+    leaf = 32
+    for n in (1024, 2048, 4096):
+        x = inputs.paper_algebraic(n)
+        bd = oracle.bdim(n, leaf)
+        for target, nn, tau_paper in rows:
+            if int(nn) != n:
+                continue
+            tau, cnt, iters = oracle.search_tau_for_valid_ratio(x, x, leaf, target / 100.0, 0.01, 20)
+            assert abs(tau - tau_paper) <= 1.5e-6, (n, target, tau, tau_paper)
+            assert abs(cnt / bd**3 - target / 100.0) <= 0.01
+            assert 1 <= iters < 20
+
+
+def test_valid_ratio_search_brute_force_small():
+    # Brute force on a tiny grid: the ratio at the returned tau is the
+    # fraction of triples whose leaf norm product is >= tau (flat test), and
+    # the mean the search starts from is the plain mean of those products.
+    n, leaf = 96, 8
+    a, b = inputs.exp_decay(n, 0.1, 30), inputs.exp_decay(n, 0.1, 31)
+    na = np.sqrt((a.astype(np.float64).reshape(12, 8, 12, 8) ** 2).sum(axis=(1, 3)))
+    nb = np.sqrt((b.astype(np.float64).reshape(12, 8, 12, 8) ** 2).sum(axis=(1, 3)))
+    prods = na[:, :, None] * nb[None, :, :]
+    assert oracle.mean_norm_product(a, b, leaf) == pytest.approx(prods.mean(), rel=1e-13)
+    for target in (0.05, 0.2, 0.5, 0.9):
+        tau, cnt, _ = oracle.search_tau_for_valid_ratio(a, b, leaf, target, 0.01, 40)
+        assert cnt == int(np.count_nonzero(prods >= tau))
+        assert abs(cnt / prods.size - target) <= 0.01
+
+
 def test_table3_no1_errors(golden):
     # Table 3 no.1: N = 1024; with tau set so that the printed fraction of leaf
     # triples is multiplied, ||AB - SpAMM||_F matches the printed error.  tau is
