@@ -119,3 +119,35 @@ def workload_exp1024() -> tuple[np.ndarray, np.ndarray]:
 def workload_alg8192(n: int = 8192) -> tuple[np.ndarray, np.ndarray]:
     """N=8192 algebraic decay 1/(1+|i-j|)^2 with random signs, A seed 0, B seed 1."""
     return algebraic_decay_signed(n, 0), algebraic_decay_signed(n, 1)
+
+
+# Learned-threshold data.
+MLP_SHAPES = ((128, 129), (128,), (128, 128), (128,), (128,), (1,))  # W1, b1, W2, b2, w3, b3
+MLP_FAN_IN = (129, 129, 128, 128, 128, 128)
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial network parameters, flat float32 in the order W1, b1, W2, b2, w3, b3:
+    each tensor uniform in [-1/sqrt(fan_in), 1/sqrt(fan_in)) of its layer, drawn
+    from (seed, tensor index, element index)."""
+    parts = []
+    for t, (shape, fan) in enumerate(zip(MLP_SHAPES, MLP_FAN_IN)):
+        k = int(np.prod(shape))
+        u = uniform01(seed, np.full(k, t, dtype=np.int64), np.arange(k, dtype=np.int64))
+        parts.append((2.0 * u - 1.0) / np.sqrt(fan))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def decay_pair_params(index: int, seed: int = 7) -> tuple[float, float, int, int]:
+    """(alpha_A, alpha_B, seed_A, seed_B) of the index-th training pair: alphas
+    uniform in [0.01, 0.5), matrix seeds distinct per pair."""
+    i = np.array([index], dtype=np.int64)
+    a1 = 0.01 + 0.49 * float(uniform01(seed, i, np.array([0]))[0])
+    a2 = 0.01 + 0.49 * float(uniform01(seed, i, np.array([1]))[0])
+    return a1, a2, 1000 + 2 * index, 1001 + 2 * index
+
+
+def log_uniform_target(index: int, lo: float = 1e-6, hi: float = 1e-2, seed: int = 11) -> float:
+    """Relative-error target of the index-th training pair, log-uniform in [lo, hi)."""
+    u = float(uniform01(seed, np.array([index], dtype=np.int64), np.array([0]))[0])
+    return float(10.0 ** (np.log10(lo) + u * (np.log10(hi) - np.log10(lo))))
