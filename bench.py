@@ -5,10 +5,14 @@ Default workload: algebraic-decay matrices A_ij = s_ij / (1 + |i-j|)^2 with
 random signs (A seed 0, B seed 1), N = 8192, FP32, leaf tiles of 64, tau = 1e-6.
 
 One step = one pass of the whole hot path over the resident inputs:
-spamm_prepare (leaf norms and pyramids of A and B, plan for tau) followed by
-spamm_execute (cost-balanced schedule and MFMA multiply of the kept pairs).
-HIP events on the stream the library launches on bracket every step and the
-multiply kernel inside it.
+spamm_prepare (leaf norms and pyramids of A and B, plan for tau), then
+spamm_execute as its two launch steps, spamm_schedule (the multiply schedule)
+and spamm_execute_scheduled (the MFMA multiply kernel of the kept pairs).  HIP
+events on the stream the library launches on bracket every step and each
+stage inside it; the roofline figure uses the multiply kernel's own time.
+
+  --write-traffic FETCH_CSV WRITE_CSV  turns two rocprofv3 --pmc runs of this
+  script into profiles/multiply_traffic.json (HBM bytes per multiply launch).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -30,7 +34,17 @@ ROOT = Path(__file__).resolve().parent
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 METRIC = "dense-equiv TFLOP/s & speedup vs dense GEMM at rel. Frobenius err ≤1e-4"
 TRAFFIC_FILE = ROOT / "profiles" / "multiply_traffic.json"
-KERNEL_SOURCE = ROOT / "paper_2103_13042_amd" / "csrc" / "kernels.hip"
+CSRC = ROOT / "paper_2103_13042_amd" / "csrc"
+CALIB_BYTES = 256 << 20  # device copy whose counter readings scale the HBM byte counters
+
+
+def multiply_kernel(n: int, leaf: int) -> tuple[str, Path]:
+    """Name and source file of the kernel spamm_execute_scheduled launches."""
+    if leaf == 64 and n % 128 == 0:
+        return "multiply_macro_dma_kernel", CSRC / "multiply_macro.hip"
+    if leaf in (32, 64):
+        return f"multiply_macro_kernel<{leaf}", CSRC / "multiply_macro.hip"
+    return f"multiply_kernel<{leaf}", CSRC / "kernels.hip"
 
 
 def log(msg: str) -> None:
@@ -49,24 +63,72 @@ def parse_args():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense FP32 GEMM comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget for the oracle's tile sample")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/multiply_traffic.json from two rocprofv3 --pmc counter files and exit")
+    ap.add_argument("--traffic-command", action="append", default=[],
+                    help="with --write-traffic: the profiling commands, recorded in the file")
     return ap.parse_args()
 
 
-def traffic_entry():
+def traffic_entry(kernel: str, source: Path, workload: str):
     """HBM bytes per multiply launch from the committed counter summary, if it
-    was taken on the current kernel source (else None)."""
+    was taken on this kernel, its current source and this workload (else None)."""
     try:
         rec = json.loads(TRAFFIC_FILE.read_text())
     except (OSError, ValueError):
         return None
-    sha = hashlib.sha256(KERNEL_SOURCE.read_bytes()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    sha = hashlib.sha256(source.read_bytes()).hexdigest()
+    if rec.get("source_sha256") != sha or rec.get("kernel") != kernel or rec.get("workload") != workload:
         return None
     return rec
 
 
+def _counter_rows(path: str, counter: str):
+    import csv
+
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") == counter:
+                yield row["Kernel_Name"], float(row["Counter_Value"])
+
+
+def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float, commands: list[str]) -> int:
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE)
+    into profiles/multiply_traffic.json: per-dispatch KiB of the multiply kernel,
+    each scaled by what the same counter reads for the CALIB_BYTES device copy."""
+    kernel, source = multiply_kernel(n, leaf)
+    out = {"kernel": kernel, "workload": workload_name(n, leaf, tau),
+           "source": str(source.relative_to(ROOT)),
+           "source_sha256": hashlib.sha256(source.read_bytes()).hexdigest(), "commands": commands}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = list(_counter_rows(path, counter))
+        ker = [v for name, v in rows if kernel in name]
+        copies = [v for name, v in rows if "copyBuffer" in name]
+        if not ker or not copies:
+            print(f"{path}: no {counter} rows for {kernel} or the calibration copy", file=sys.stderr)
+            return 1
+        calib = max(copies)  # the CALIB_BYTES copy is the largest copy dispatch
+        scale = (CALIB_BYTES / 1024.0) / calib
+        key = counter.split("_")[0].lower()
+        out[f"{key}_kib_per_dispatch"] = float(np.mean(ker))
+        out[f"{key}_dispatches"] = len(ker)
+        out[f"{key}_calib_kib"] = calib
+        out[f"{key}_scale"] = scale
+    out["hbm_bytes_per_launch"] = round(1024.0 * (out["fetch_kib_per_dispatch"] * out["fetch_scale"]
+                                                  + out["write_kib_per_dispatch"] * out["write_scale"]))
+    TRAFFIC_FILE.write_text(json.dumps(out, indent=1) + "\n")
+    print(json.dumps(out, indent=1))
+    return 0
+
+
+def workload_name(n: int, leaf: int, tau: float) -> str:
+    return f"algebraic-decay s_ij/(1+|i-j|)^2, N={n}, leaf {leaf}, tau={tau:g}"
+
+
 def main() -> int:
     args = parse_args()
+    if args.write_traffic:
+        return write_traffic(*args.write_traffic, args.n, args.leaf, args.tau, args.traffic_command)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(
@@ -100,43 +162,51 @@ def main() -> int:
     bufs = sp.plan_buffers(n, leaf, dev)
 
     # a device-to-device copy of known size, for scaling HBM byte counters
-    calib = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    calib = torch.empty(CALIB_BYTES, dtype=torch.uint8, device=dev)
     calib_dst = torch.empty_like(calib)
     calib_dst.copy_(calib)
     torch.cuda.synchronize()
 
+    # One step = the whole hot path: norms, pyramids, plan (spamm_prepare), then
+    # spamm_execute as its two launch steps, so that events on the stream the
+    # library launches on (torch's current stream, passed by the binding)
+    # bracket the multiply kernel alone.
     def step(t):
         offsets, klist, _ = sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
-        sp.execute(a, b, leaf, offsets, klist, c=c, ws=ws)
+        sp.schedule(offsets, klist, n, leaf, ws=ws)
+        sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
 
     def timed(t, steps, warmup):
         for _ in range(warmup):
             step(t)
         torch.cuda.synchronize()
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record()
         for e in ev:
             e[0].record()
             offsets, klist, _ = sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
             e[1].record()
-            sp.execute(a, b, leaf, offsets, klist, c=c, ws=ws)
+            sp.schedule(offsets, klist, n, leaf, ws=ws)
             e[2].record()
+            sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
+            e[3].record()
         end.record()
         torch.cuda.synchronize()
         total = start.elapsed_time(end)
-        prep = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-        exe = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        stages = [float(np.mean([e[q].elapsed_time(e[q + 1]) for e in ev])) for q in range(3)]
         pairs = int(bufs[2].item())
-        return total / steps, prep, exe, pairs
+        return total / steps, stages, pairs
 
+    kname, ksrc = multiply_kernel(n, leaf)
+    workload = workload_name(n, leaf, tau)
     log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
-    ms_step, prep_ms, exec_ms, pairs = timed(tau, args.steps, args.warmup)
+    ms_step, (prep_ms, sched_ms, kern_ms), pairs = timed(tau, args.steps, args.warmup)
     dense_equiv = 2.0 * n**3 / (ms_step * 1e-3) / 1e12
     flops_mul = 2.0 * leaf**3 * pairs
-    achieved = flops_mul / (exec_ms * 1e-3) / 1e12
-    log(f"{ms_step:.3f} ms/step (prepare {prep_ms:.3f}, multiply {exec_ms:.3f}), pairs {pairs}, "
-        f"{dense_equiv:.1f} dense-equiv TFLOP/s, multiply {achieved:.1f} TFLOP/s")
+    achieved = flops_mul / (kern_ms * 1e-3) / 1e12
+    log(f"{ms_step:.3f} ms/step (prepare {prep_ms:.3f}, schedule {sched_ms:.3f}, {kname} {kern_ms:.3f}), "
+        f"pairs {pairs}, {dense_equiv:.1f} dense-equiv TFLOP/s, multiply {achieved:.1f} TFLOP/s")
 
     result = {
         "metric": METRIC,
@@ -152,20 +222,22 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"algebraic-decay s_ij/(1+|i-j|)^2, N={n}, leaf {leaf}, tau={tau:g}",
+            "workload": workload,
             "n": n,
             "leaf": leaf,
             "tau": tau,
             "pairs": pairs,
             "valid_ratio": pairs / bd**3,
         },
-        "stages_ms": {"prepare": round(prep_ms, 4), "multiply": round(exec_ms, 4)},
+        "stages_ms": {"prepare": round(prep_ms, 4), "schedule": round(sched_ms, 4), "multiply": round(kern_ms, 4)},
     }
 
-    tr = traffic_entry()
+    tr = traffic_entry(kname, ksrc, workload)
     result["roofline"] = {
         "bound": "mfma",
-        "kernel": f"multiply_kernel<{leaf}>",
+        "kernel": kname,
+        "flop_per_launch": flops_mul,
+        "ms_per_launch": round(kern_ms, 4),
         "achieved": round(achieved, 3),
         "peak": PEAK_FP32_MFMA_TFLOPS,
         "unit": "TFLOP/s",
@@ -200,7 +272,7 @@ def main() -> int:
     sweep = {}
     for tok in [s for s in args.sweep.split(",") if s.strip()]:
         t = float(tok)
-        ms, pm, em, p = timed(t, max(5, args.steps // 2), 2)
+        ms, (_, _, em), p = timed(t, max(5, args.steps // 2), 2)
         sweep[f"{t:g}"] = {
             "ms_per_step": round(ms, 4),
             "dense_equiv_tflops": round(2.0 * n**3 / (ms * 1e-3) / 1e12, 3),

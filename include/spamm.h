@@ -115,6 +115,20 @@ spamm_status spamm_plan(const double* pyr_a, const double* pyr_b, int64_t n, int
 spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t leaf, const int32_t* offsets,
                            const int32_t* klist, float* c, void* workspace, size_t workspace_bytes, void* stream);
 
+/* spamm_execute in its two launch steps, for callers that time the multiply
+ * kernel on its own.  spamm_schedule derives from a plan what the multiply
+ * kernel streams (for leaf 32 and 64: per 2x2 block of output tiles the four
+ * k-bitmaps and the size of their union, and the prefix of those sizes; for
+ * leaf 128 nothing) and keeps it in the workspace; spamm_execute_scheduled
+ * then launches the multiply kernel alone.  The pair equals spamm_execute when
+ * both get the same plan and workspace with no other call on that workspace
+ * in between.  Arguments and errors as spamm_execute (section 3.3, 3.5.1). */
+spamm_status spamm_schedule(const int32_t* offsets, const int32_t* klist, int64_t n, int32_t leaf, void* workspace,
+                            size_t workspace_bytes, void* stream);
+spamm_status spamm_execute_scheduled(const float* a, const float* b, int64_t n, int32_t leaf, const int32_t* offsets,
+                                     const int32_t* klist, float* c, void* workspace, size_t workspace_bytes,
+                                     void* stream);
+
 /* The first half of the hot path for one product: leaf norms and pyramids of A
  * and B (one launch each for both matrices) and the plan for tau, as
  * spamm_pyramid and spamm_plan would produce them.  The pyramids stay in the

@@ -10,7 +10,8 @@ from __future__ import annotations
 
 __all__ = [
     "bdim", "levels", "pyramid_size", "leaf_supported", "workspace_bytes", "workspace",
-    "norms", "pyramid", "pyramid_levels", "plan", "plan_buffers", "prepare", "execute", "multiply",
+    "norms", "pyramid", "pyramid_levels", "plan", "plan_buffers", "prepare", "execute", "schedule",
+    "execute_scheduled", "multiply",
     "search_valid_ratio", "SpammError",
 ]
 

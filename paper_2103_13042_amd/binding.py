@@ -35,6 +35,8 @@ _SIGS = {
     "spamm_pyramid": (_st, [_vp, _i64, _i32, _vp, _vp, _sz, _vp]),
     "spamm_plan": (_st, [_vp, _vp, _i64, _i32, _f64, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "spamm_execute": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_schedule": (_st, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "spamm_execute_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "spamm_multiply": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _vp, _sz, _vp]),
     "spamm_search_valid_ratio": (_st, [_vp, _vp, _i64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -201,19 +203,54 @@ def prepare(a, b, tau: float, leaf: int, *, bufs=None, ws=None):
     return offsets, klist, pairs
 
 
+def _check_plan(offsets, klist, n: int, leaf: int, dev) -> None:
+    b = bdim(n, leaf)
+    for name, t, need in (("offsets", offsets, b * b + 1), ("klist", klist, 1)):
+        if t.dtype != torch.int32 or t.device != dev or not t.is_contiguous() or t.numel() < need:
+            raise ValueError(f"{name}: expected a contiguous int32 tensor on {dev} with >= {need} entries")
+
+
+def _mul_operands(a, b, leaf, offsets, klist, c, ws):
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n or b.device != a.device:
+        raise ValueError("a and b must have the same size and device")
+    _check_plan(offsets, klist, n, leaf, a.device)
+    c = torch.empty_like(a) if c is None else c
+    if _square_f32(c, "c") != n or c.device != a.device:
+        raise ValueError("c must match a")
+    ws = workspace(n, leaf, a.device) if ws is None else ws
+    return n, c, ws
+
+
 def execute(a, b, leaf: int, offsets, klist, *, c=None, ws=None) -> torch.Tensor:
     """Multiply the kept pairs of a plan into C (spamm_execute)."""
-    n = _square_f32(a, "a")
-    if _square_f32(b, "b") != n:
-        raise ValueError("a and b must have the same size")
-    c = torch.empty_like(a) if c is None else c
-    _square_f32(c, "c")
-    ws = workspace(n, leaf, a.device) if ws is None else ws
+    n, c, ws = _mul_operands(a, b, leaf, offsets, klist, c, ws)
     _check(
         _lib.spamm_execute(
             _ptr(a), _ptr(b), n, leaf, _ptr(offsets), _ptr(klist), _ptr(c), _ptr(ws), ws.numel(), _stream(a.device)
         ),
         "spamm_execute",
+    )
+    return c
+
+
+def schedule(offsets, klist, n: int, leaf: int, *, ws=None) -> None:
+    """First launch step of execute: the multiply schedule into the workspace (spamm_schedule)."""
+    dev = offsets.device
+    _check_plan(offsets, klist, n, leaf, dev)
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    _check(_lib.spamm_schedule(_ptr(offsets), _ptr(klist), n, leaf, _ptr(ws), ws.numel(), _stream(dev)),
+           "spamm_schedule")
+
+
+def execute_scheduled(a, b, leaf: int, offsets, klist, *, c=None, ws=None) -> torch.Tensor:
+    """Second launch step of execute: the multiply kernel alone (spamm_execute_scheduled)."""
+    n, c, ws = _mul_operands(a, b, leaf, offsets, klist, c, ws)
+    _check(
+        _lib.spamm_execute_scheduled(
+            _ptr(a), _ptr(b), n, leaf, _ptr(offsets), _ptr(klist), _ptr(c), _ptr(ws), ws.numel(), _stream(a.device)
+        ),
+        "spamm_execute_scheduled",
     )
     return c
 

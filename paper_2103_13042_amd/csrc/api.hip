@@ -9,9 +9,11 @@
 #include <mutex>
 
 #include "spamm.h"
+#include "host.h"
 #include "internal.h"
 
-namespace {
+namespace spamm_host {
+
 
 thread_local char g_last_error[512] = "";
 
@@ -28,12 +30,6 @@ spamm_status hip_check(hipError_t e, const char* what) {
     return fail(SPAMM_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), int(e));
 }
 
-// Tile geometry of an n x n problem with leaf tiles of edge `leaf`.
-struct Geom {
-    int64_t n = 0, bdim = 0, side = 0, ntiles = 0, pyr = 0;
-    int32_t leaf = 0, lv = 0, nwords = 0;
-};
-
 bool make_geom(int64_t n, int32_t leaf, Geom* g) {
     if (n <= 0 || leaf <= 0 || leaf > 1024) return false;
     g->n = n;
@@ -49,14 +45,10 @@ bool make_geom(int64_t n, int32_t leaf, Geom* g) {
     return true;
 }
 
+namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Workspace regions, in order.  Every entry point uses a subset.
-struct Layout {
-    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix, pairs,
-        scalars, total;
-};
+}  // namespace
 
 Layout make_layout(const Geom& g) {
     Layout L{};
@@ -80,14 +72,10 @@ Layout make_layout(const Geom& g) {
     L.mcount = take(sizeof(int32_t) * nm);
     L.mprefix = take(sizeof(int32_t) * (nm + 1));
     L.pairs = take(sizeof(int64_t));
-    L.scalars = take(2 * sizeof(double));
+    L.scalars = take(4 * sizeof(double));
+    L.partials = take(sizeof(double) * 1024);
     L.total = o;
     return L;
-}
-
-template <typename T>
-T* at(void* ws, size_t off) {
-    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
 bool overlaps(const void* p, size_t pbytes, const void* q, size_t qbytes) {
@@ -132,7 +120,6 @@ spamm_status check_tau(double tau) {
     return SPAMM_OK;
 }
 
-// Enqueue the norm pass and pyramid for nmat matrices whose pyramids go to pyr_out[m].
 spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
                               hipStream_t s) {
     const Layout L = make_layout(g);
@@ -154,14 +141,14 @@ spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, do
     return hip_check(spamm::launch_pyramid(pj, nmat, g.bdim, g.lv, s), "pyramid kernel");
 }
 
-spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, double tau, int32_t* offsets,
-                          int32_t* klist, int64_t* pairs, void* ws, hipStream_t s) {
+spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, double tau, bool skipped,
+                          int32_t* offsets, int32_t* klist, int64_t* pairs, void* ws, hipStream_t s) {
     const Layout L = make_layout(g);
     uint64_t* masks = at<uint64_t>(ws, L.masks);
     int32_t* counts = at<int32_t>(ws, L.counts);
     int32_t* bsums = at<int32_t>(ws, L.bsums);
     int32_t* boffs = at<int32_t>(ws, L.boffs);
-    spamm_status st = hip_check(spamm::launch_plan_mask(pa, pb, g.bdim, g.lv, tau, masks, counts, bsums, s),
+    spamm_status st = hip_check(spamm::launch_plan_mask(pa, pb, g.bdim, g.lv, tau, skipped, masks, counts, bsums, s),
                                 "plan mask kernel");
     if (st != SPAMM_OK) return st;
     st = hip_check(spamm::launch_plan_scan(bsums, g.bdim * g.nwords, boffs, offsets, g.ntiles, pairs, s),
@@ -180,7 +167,38 @@ spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const
     return SPAMM_OK;
 }
 
-}  // namespace
+
+spamm_status enqueue_schedule(const Geom& g, const int32_t* offsets, const int32_t* klist, void* ws, hipStream_t s) {
+    if (g.leaf != 32 && g.leaf != 64) return SPAMM_OK;  // the single-tile kernel reads the plan directly
+    const Layout L = make_layout(g);
+    return hip_check(spamm::launch_macro_schedule(offsets, klist, g.bdim, at<uint64_t>(ws, L.mwords),
+                                                  at<int32_t>(ws, L.mcount), at<int32_t>(ws, L.mprefix), s),
+                     "macro schedule kernels");
+}
+
+spamm_status enqueue_multiply(const Geom& g, const float* a, const float* b, const int32_t* offsets,
+                              const int32_t* klist, float* c, void* ws, hipStream_t s) {
+    const bool vec = (g.n % 4) == 0 && aligned16(a) && aligned16(b);
+    const Layout L = make_layout(g);
+    if (g.leaf == 32 || g.leaf == 64)
+        return hip_check(spamm::launch_macro_multiply(a, b, c, g.n, g.leaf, g.bdim, at<uint64_t>(ws, L.mwords),
+                                                      at<int32_t>(ws, L.mprefix), vec, device_cus(), s),
+                         "macro multiply kernel");
+    return hip_check(spamm::launch_multiply(a, b, c, g.n, g.leaf, g.bdim, offsets, klist,
+                                            at<int32_t>(ws, L.pair_scratch), vec, device_cus(), s),
+                     "multiply kernel");
+}
+
+spamm_status enqueue_execute(const Geom& g, const float* a, const float* b, const int32_t* offsets,
+                             const int32_t* klist, float* c, void* ws, hipStream_t s) {
+    spamm_status st = enqueue_schedule(g, offsets, klist, ws, s);
+    if (st != SPAMM_OK) return st;
+    return enqueue_multiply(g, a, b, offsets, klist, c, ws, s);
+}
+
+}  // namespace spamm_host
+
+using namespace spamm_host;
 
 extern "C" {
 
@@ -250,7 +268,7 @@ spamm_status spamm_plan(const double* pyr_a, const double* pyr_b, int64_t n, int
     if (klist_capacity < g.ntiles * g.bdim)
         return fail(SPAMM_ENOSPACE, "klist capacity %lld < bdim^3 = %lld", (long long)klist_capacity,
                     (long long)(g.ntiles * g.bdim));
-    return enqueue_plan(g, pyr_a, pyr_b, tau, offsets, klist, pairs, workspace, static_cast<hipStream_t>(stream));
+    return enqueue_plan(g, pyr_a, pyr_b, tau, false, offsets, klist, pairs, workspace, static_cast<hipStream_t>(stream));
 }
 
 spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t leaf, const int32_t* offsets,
@@ -263,18 +281,35 @@ spamm_status spamm_execute(const float* a, const float* b, int64_t n, int32_t le
     if (!offsets || !klist) return fail(SPAMM_EINVAL, "null plan pointer");
     if ((st = check_grid(g)) != SPAMM_OK) return st;
     if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
-    const bool vec = (n % 4) == 0 && aligned16(a) && aligned16(b);
-    const Layout L = make_layout(g);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (leaf == 32 || leaf == 64)
-        return hip_check(spamm::launch_multiply_macro(a, b, c, n, leaf, g.bdim, offsets, klist,
-                                                      at<uint64_t>(workspace, L.mwords),
-                                                      at<int32_t>(workspace, L.mcount),
-                                                      at<int32_t>(workspace, L.mprefix), vec, device_cus(), s),
-                         "macro multiply kernels");
-    return hip_check(spamm::launch_multiply(a, b, c, n, leaf, g.bdim, offsets, klist,
-                                            at<int32_t>(workspace, L.pair_scratch), vec, device_cus(), s),
-                     "multiply kernel");
+    return enqueue_execute(g, a, b, offsets, klist, c, workspace, static_cast<hipStream_t>(stream));
+}
+
+spamm_status spamm_schedule(const int32_t* offsets, const int32_t* klist, int64_t n, int32_t leaf, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!offsets || !klist) return fail(SPAMM_EINVAL, "null plan pointer");
+    if (!spamm_leaf_supported(leaf))
+        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (32, 64, 128)", leaf);
+    spamm_status st = check_grid(g);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    return enqueue_schedule(g, offsets, klist, workspace, static_cast<hipStream_t>(stream));
+}
+
+spamm_status spamm_execute_scheduled(const float* a, const float* b, int64_t n, int32_t leaf, const int32_t* offsets,
+                                     const int32_t* klist, float* c, void* workspace, size_t workspace_bytes,
+                                     void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_mul_args(g, a, b, c);
+    if (st != SPAMM_OK) return st;
+    if (!offsets || !klist) return fail(SPAMM_EINVAL, "null plan pointer");
+    if ((st = check_grid(g)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    return enqueue_multiply(g, a, b, offsets, klist, c, workspace, static_cast<hipStream_t>(stream));
 }
 
 spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau, int32_t leaf, int32_t* offsets,
@@ -298,7 +333,7 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
     const float* xs[2] = {a, b};
     double* ps[2] = {pa, pb};
     if ((st = enqueue_pyramids(g, xs, 2, ps, workspace, s)) != SPAMM_OK) return st;
-    return enqueue_plan(g, pa, pb, tau, offsets, klist, pairs, workspace, s);
+    return enqueue_plan(g, pa, pb, tau, false, offsets, klist, pairs, workspace, s);
 }
 
 spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,

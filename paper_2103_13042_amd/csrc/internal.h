@@ -35,7 +35,8 @@ hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv,
 
 // Plan: per output tile, the ballot bitmap of kept k (words of 64) and its
 // count V; per block of 64 tiles (i, 64*jb ..) the sum of V (block b = i*nw + jb).
-hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+// With `skipped` the bitmaps select the dropped triples instead.
+hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau, bool skipped,
                             uint64_t* masks, int32_t* counts, int32_t* block_sums, hipStream_t s);
 // Plan counts only (no bitmaps): per block of 64 tiles the number of kept triples.
 hipError_t launch_plan_count(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
@@ -59,11 +60,14 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
                            const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
                            int num_cus, hipStream_t s);
 
-// Multiply on 2x2 macro tiles (leaf 32 and 64): per-macro-tile k bitmaps into
-// words [mb*mb*4*nwords], union sizes into ucount [mb*mb], their exclusive
-// prefix into uprefix [mb*mb + 1], then the persistent multiply.
-hipError_t launch_multiply_macro(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const int32_t* offsets, const int32_t* klist, uint64_t* words, int32_t* ucount,
-                                 int32_t* uprefix, bool vec, int num_cus, hipStream_t s);
+// Multiply on 2x2 macro tiles (leaf 32 and 64), in two launches.  Schedule:
+// per-macro-tile k bitmaps into words [mb*mb*4*nwords], union sizes into
+// ucount [mb*mb], their exclusive prefix into uprefix [mb*mb + 1].  Multiply:
+// the persistent kernel over that schedule.
+hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, uint64_t* words,
+                                 int32_t* ucount, int32_t* uprefix, hipStream_t s);
+hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
+                                 const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
+                                 hipStream_t s);
 
 }  // namespace spamm

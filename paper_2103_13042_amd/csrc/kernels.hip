@@ -181,14 +181,18 @@ hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv,
 // --------------------------------------------------------------------------
 // Plan.  Block (jb, i) owns the 64 output tiles (i, 64*jb .. 64*jb+63) and
 // walks k in chunks of 64.  A chunk is one pyramid node of 64 x 64 leaf tiles
-// (level Lv-6) on each side; when that node product is below tau the chunk is
-// skipped for all 64 tiles at once (uniform branch).  Otherwise the chunk's
-// 64 x 64 block of B leaf norms is staged in LDS, each lane takes one k, and
-// one ballot per tile gives the 64-bit bitmap of kept k.
+// (level Lv-6) on each side; when that node product is below tau every leaf
+// product in the chunk is too (a node norm bounds the norms below it), so the
+// chunk is settled for all 64 tiles at once (uniform branch).  Otherwise the
+// chunk's 64 x 64 block of B leaf norms is staged in LDS, each lane takes one
+// k, and one ballot per tile gives the 64-bit bitmap of selected k.
+//
+// SKIPPED selects the complement: the triples whose product is below tau, the
+// pairs SpAMM drops (their product sum is the error matrix AB - SpAMM).
 
 constexpr int kPlanThreads = 256;
 
-template <bool MASKS>
+template <bool MASKS, bool SKIPPED>
 __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* __restrict__ pyr_a,
                                                                  const double* __restrict__ pyr_b, int64_t bdim,
                                                                  int lv, double tau, uint64_t* __restrict__ masks,
@@ -206,22 +210,25 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
 #pragma unroll
     for (int u = 0; u < 16; ++u) cnt[u] = 0;
     for (int c = 0; c < nw; ++c) {
-        bool keep;
+        bool below;
         if (lv >= 6) {
             const int lc = lv - 6;
             const int64_t w = int64_t(1) << lc;
-            keep = pyr_a[level_offset(lc) + (i >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + (j0 >> 6)] >=
-                   tau;
+            below = !(pyr_a[level_offset(lc) + (i >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + (j0 >> 6)] >=
+                      tau);
         } else {
-            keep = pyr_a[0] * pyr_b[0] >= tau;
+            below = !(pyr_a[0] * pyr_b[0] >= tau);
         }
-        if (!keep) {
-            if (MASKS) {
+        if (below) {
+            // every real triple of the chunk is dropped: none selected, or all
+            // of them in the complement
+            const int64_t k = int64_t(c) * 64 + lane;
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int64_t j = j0 + wave + 4 * u;
-                    if (lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = 0ull;
-                }
+            for (int u = 0; u < 16; ++u) {
+                const int64_t j = j0 + wave + 4 * u;
+                const uint64_t mk = SKIPPED ? __ballot(k < bdim && j < bdim) : 0ull;
+                if (MASKS && lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = mk;
+                cnt[u] += __popcll(mk);
             }
             continue;
         }
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
             const int jj = wave + 4 * u;
             const int64_t j = j0 + jj;
             const double p = a * sb[lane][jj];
-            const bool bit = (p >= tau) && (k < bdim) && (j < bdim);
+            const bool bit = (SKIPPED ? !(p >= tau) : (p >= tau)) && (k < bdim) && (j < bdim);
             const uint64_t mk = __ballot(bit);
             if (MASKS && lane == 0 && j < bdim) masks[(i * bdim + j) * nw + c] = mk;
             cnt[u] += __popcll(mk);
@@ -267,17 +274,23 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
     if (threadIdx.x == 0) block_sums[i * nw + blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau, bool skipped,
                             uint64_t* masks, int32_t* counts, int32_t* block_sums, hipStream_t s) {
     dim3 grid{unsigned((bdim + 63) / 64), unsigned(bdim), 1u};
-    plan_mask_kernel<true><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts, block_sums);
+    if (skipped)
+        plan_mask_kernel<true, true><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts,
+                                                                   block_sums);
+    else
+        plan_mask_kernel<true, false><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, masks, counts,
+                                                                    block_sums);
     return hipGetLastError();
 }
 
 hipError_t launch_plan_count(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
                              int32_t* block_sums, hipStream_t s) {
     dim3 grid{unsigned((bdim + 63) / 64), unsigned(bdim), 1u};
-    plan_mask_kernel<false><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, nullptr, nullptr, block_sums);
+    plan_mask_kernel<false, false><<<grid, kPlanThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, nullptr, nullptr,
+                                                                 block_sums);
     return hipGetLastError();
 }
 

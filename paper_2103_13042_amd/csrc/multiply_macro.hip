@@ -331,7 +331,7 @@ constexpr int kDmaStores = 16;  // per wave per macro tile
 #define SPAMM_DMA_KC 32
 #endif
 #ifndef SPAMM_DMA_STAGES
-#define SPAMM_DMA_STAGES 4
+#define SPAMM_DMA_STAGES 2
 #endif
 constexpr int kDmaKC = SPAMM_DMA_KC;          // k per item
 constexpr int kDmaStages = SPAMM_DMA_STAGES;  // LDS stages (items in flight + 1)
@@ -537,17 +537,22 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
 }
 
-template <int LEAF>
-static hipError_t launch_macro(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
-                               const int32_t* offsets, const int32_t* klist, uint64_t* words, int32_t* ucount,
-                               int32_t* uprefix, bool vec, int num_cus, hipStream_t s) {
+hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, uint64_t* words,
+                                 int32_t* ucount, int32_t* uprefix, hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int nw = int((bdim + 63) / 64);
     macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, words, ucount);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_plan_scan(ucount, nm, uprefix, uprefix, nm, nullptr, s);
-    if (e != hipSuccess) return e;
+    return launch_plan_scan(ucount, nm, uprefix, uprefix, nm, nullptr, s);
+}
+
+template <int LEAF>
+static hipError_t launch_macro_run(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                                   const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
+                                   hipStream_t s) {
+    const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
+    const int nw = int((bdim + 63) / 64);
     const int64_t cap = ((nm + 7) / 8) * 8;
     if (LEAF == 64 && vec && n % 128 == 0) {
         int64_t groups = int64_t(num_cus);
@@ -568,12 +573,12 @@ static hipError_t launch_macro(const float* a, const float* b, float* c, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_multiply_macro(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const int32_t* offsets, const int32_t* klist, uint64_t* words, int32_t* ucount,
-                                 int32_t* uprefix, bool vec, int num_cus, hipStream_t s) {
+hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
+                                 const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
+                                 hipStream_t s) {
     switch (leaf) {
-        case 32: return launch_macro<32>(a, b, c, n, bdim, offsets, klist, words, ucount, uprefix, vec, num_cus, s);
-        case 64: return launch_macro<64>(a, b, c, n, bdim, offsets, klist, words, ucount, uprefix, vec, num_cus, s);
+        case 32: return launch_macro_run<32>(a, b, c, n, bdim, words, uprefix, vec, num_cus, s);
+        case 64: return launch_macro_run<64>(a, b, c, n, bdim, words, uprefix, vec, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -301,6 +301,21 @@ def test_staged_calls_equal_the_fused_call(c1):
     assert torch.equal(sp.execute(ga, gb, 32, o2, k2), c_fused)
 
 
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 32), (2048, 64), (1100, 64), (1024, 128)])
+def test_schedule_then_multiply_kernel_equals_execute(n, leaf):
+    a, b = inputs.exp_decay(n, 0.05, 50), inputs.exp_decay(n, 0.05, 51)
+    ga, gb = gpu(a), gpu(b)
+    ws = sp.workspace(n, leaf, DEV)
+    offsets, klist, _ = sp.prepare(ga, gb, 1e-6, leaf, ws=ws)
+    c_exec = sp.execute(ga, gb, leaf, offsets, klist, ws=ws)
+    sp.schedule(offsets, klist, n, leaf, ws=ws)
+    c_two = sp.execute_scheduled(ga, gb, leaf, offsets, klist, ws=ws)
+    assert torch.equal(c_exec, c_two)
+    # the multiply kernel alone, run again on the same schedule
+    c_again = sp.execute_scheduled(ga, gb, leaf, offsets, klist, ws=ws)
+    assert torch.equal(c_exec, c_again)
+
+
 @pytest.mark.parametrize("tau", [1e-8, 1e-6, 1e-4])
 def test_algebraic_8192_full_size_sampled_tiles(tau, alg8192):
     """The benchmark workload at full size and in the benchmark's launch
