@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(str(LIB_PATH))
 
 _i64, _i32, _f64, _vp, _sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 _st = ctypes.c_int
+_f32 = ctypes.c_float
 
 _SIGS = {
     "spamm_bdim": (_i64, [_i64, _i32]),
@@ -40,6 +41,17 @@ _SIGS = {
     "spamm_prepare": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "spamm_multiply": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _vp, _sz, _vp]),
     "spamm_search_valid_ratio": (_st, [_vp, _vp, _i64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_mlp_param_count": (_i64, []),
+    "spamm_mlp_acts_floats": (_i64, [_i32]),
+    "spamm_tau_features": (_st, [_vp, _vp, _i64, _i32, _f64, _vp, _vp]),
+    "spamm_mlp_forward": (_st, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "spamm_mlp_loss_grad": (_st, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "spamm_mlp_adam": (_st, [_vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp]),
+    "spamm_sumsq_scratch_bytes": (_sz, []),
+    "spamm_sumsq": (_st, [_vp, _i64, _vp, _vp, _sz, _vp]),
+    "spamm_error_for_tau": (_st, [_vp, _vp, _i64, _i32, _f64, _vp, _vp, _f64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_search_tau_for_error": (
+        _st, [_vp, _vp, _i64, _i32, _f64, _f64, _i32, _vp, _vp, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_strerror": (ctypes.c_char_p, [_st]),
     "spamm_last_error": (ctypes.c_char_p, []),
 }
@@ -294,3 +306,123 @@ def search_valid_ratio(pyr_a, pyr_b, n: int, leaf: int, target: float, tol: floa
         "spamm_search_valid_ratio",
     )
     return tau.value, pairs.value, iters.value
+
+
+# -- threshold for an error target, and the network that predicts it -------
+
+
+def mlp_param_count() -> int:
+    return int(_lib.spamm_mlp_param_count())
+
+
+def _dev_f32(t, name: str, numel: int | None = None):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous CUDA float32 tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs >= {numel} entries")
+
+
+def mlp_acts(batch: int, device) -> torch.Tensor:
+    return torch.empty(int(_lib.spamm_mlp_acts_floats(batch)), dtype=torch.float32, device=device)
+
+
+def tau_features(pyr_a, pyr_b, n: int, leaf: int, target: float, *, out=None) -> torch.Tensor:
+    """FP32 [129] features of one problem (spamm_tau_features)."""
+    dev = pyr_a.device
+    out = torch.empty(129, dtype=torch.float32, device=dev) if out is None else out
+    _dev_f32(out, "out", 129)
+    _check(_lib.spamm_tau_features(_ptr(pyr_a), _ptr(pyr_b), n, leaf, float(target), _ptr(out), _stream(dev)),
+           "spamm_tau_features")
+    return out
+
+
+def mlp_forward(params, x, *, y=None, acts=None) -> torch.Tensor:
+    """Predicted log10(tau) for rows x [B, 129] (spamm_mlp_forward)."""
+    batch = x.shape[0]
+    _dev_f32(params, "params", mlp_param_count())
+    _dev_f32(x, "x", batch * 129)
+    y = torch.empty(batch, dtype=torch.float32, device=x.device) if y is None else y
+    acts = mlp_acts(batch, x.device) if acts is None else acts
+    _dev_f32(y, "y", batch)
+    _dev_f32(acts, "acts", int(_lib.spamm_mlp_acts_floats(batch)))
+    _check(_lib.spamm_mlp_forward(_ptr(params), _ptr(x), batch, _ptr(y), _ptr(acts), _stream(x.device)),
+           "spamm_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(params, x, t, *, acts=None, grad=None, loss=None):
+    """(loss [1], grad [P]) of the mean squared log10(tau) error (spamm_mlp_loss_grad)."""
+    batch = x.shape[0]
+    _dev_f32(params, "params", mlp_param_count())
+    _dev_f32(x, "x", batch * 129)
+    _dev_f32(t, "t", batch)
+    acts = mlp_acts(batch, x.device) if acts is None else acts
+    grad = torch.empty_like(params) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=x.device) if loss is None else loss
+    _dev_f32(acts, "acts", int(_lib.spamm_mlp_acts_floats(batch)))
+    _dev_f32(grad, "grad", mlp_param_count())
+    _dev_f32(loss, "loss", 1)
+    _check(_lib.spamm_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(t), batch, _ptr(acts), _ptr(grad), _ptr(loss),
+                                    _stream(x.device)), "spamm_mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8) -> None:
+    """One Adam step in place on params, m, v (spamm_mlp_adam)."""
+    p = mlp_param_count()
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _dev_f32(t, name, p)
+    _check(_lib.spamm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                               float(beta2), float(eps), _stream(params.device)), "spamm_mlp_adam")
+
+
+def sumsq(x, *, out=None, scratch=None) -> torch.Tensor:
+    """Sum of squares of an FP32 tensor in FP64, as a device tensor [1] (spamm_sumsq)."""
+    _dev_f32(x, "x")
+    dev = x.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    nb = int(_lib.spamm_sumsq_scratch_bytes())
+    scratch = torch.empty(nb, dtype=torch.uint8, device=dev) if scratch is None else scratch
+    _check(_lib.spamm_sumsq(_ptr(x), x.numel(), _ptr(out), _ptr(scratch), scratch.numel(), _stream(dev)),
+           "spamm_sumsq")
+    return out
+
+
+def _tau_args(a, b, leaf, pyr_a, pyr_b, e, ws):
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    size = pyramid_size(n, leaf)
+    for name, p in (("pyr_a", pyr_a), ("pyr_b", pyr_b)):
+        if p.dtype != torch.float64 or not p.is_cuda or not p.is_contiguous() or p.numel() != size:
+            raise ValueError(f"{name}: expected a contiguous CUDA float64 pyramid of {size} entries")
+    e = torch.empty_like(a) if e is None else e
+    _square_f32(e, "e")
+    ws = workspace(n, leaf, a.device) if ws is None else ws
+    return n, e, ws
+
+
+def error_for_tau(a, b, tau: float, leaf: int, pyr_a, pyr_b, ab_sumsq: float, *, e=None, ws=None):
+    """(||AB - SpAMM||_F / ||AB||_F, dropped triples) at tau (spamm_error_for_tau)."""
+    n, e, ws = _tau_args(a, b, leaf, pyr_a, pyr_b, e, ws)
+    err = ctypes.c_double(0.0)
+    dropped = ctypes.c_int64(0)
+    _check(_lib.spamm_error_for_tau(_ptr(a), _ptr(b), n, leaf, float(tau), _ptr(pyr_a), _ptr(pyr_b),
+                                    float(ab_sumsq), _ptr(e), ctypes.byref(err), ctypes.byref(dropped), _ptr(ws),
+                                    ws.numel(), _stream(a.device)), "spamm_error_for_tau")
+    return err.value, dropped.value
+
+
+def search_tau_for_error(a, b, leaf: int, target: float, pyr_a, pyr_b, ab_sumsq: float, *, guess: float = 0.0,
+                         max_evals: int = 64, e=None, ws=None):
+    """Largest norm product tau with relative error <= target: (tau, err, pairs, evals)
+    (spamm_search_tau_for_error)."""
+    n, e, ws = _tau_args(a, b, leaf, pyr_a, pyr_b, e, ws)
+    tau, err = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    pairs, evals = ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(_lib.spamm_search_tau_for_error(
+        _ptr(a), _ptr(b), n, leaf, float(target), float(guess), int(max_evals), _ptr(pyr_a), _ptr(pyr_b),
+        float(ab_sumsq), _ptr(e), ctypes.byref(tau), ctypes.byref(err), ctypes.byref(pairs), ctypes.byref(evals),
+        _ptr(ws), ws.numel(), _stream(a.device)), "spamm_search_tau_for_error")
+    return tau.value, err.value, pairs.value, evals.value

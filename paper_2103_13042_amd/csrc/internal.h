@@ -70,4 +70,52 @@ hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64
                                  const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
                                  hipStream_t s);
 
+// --------------------------------------------------------------------------
+// Learned threshold (learned.hip).
+
+constexpr int kSumBlocks = 1024;  // partials of launch_sumsq
+constexpr int kMlpIn = 129, kMlpHid = 128;
+
+// Offsets into the flat parameter array and into the activation scratch of
+// a batch (in floats).
+struct MlpLayout {
+    int64_t w1 = 0;
+    int64_t b1 = w1 + int64_t(kMlpHid) * kMlpIn;
+    int64_t w2 = b1 + kMlpHid;
+    int64_t b2 = w2 + int64_t(kMlpHid) * kMlpHid;
+    int64_t w3 = b2 + kMlpHid;
+    int64_t b3 = w3 + kMlpHid;
+    int64_t count = b3 + 1;
+    // activations: Z1 H1 Z2 H2 D1 D2 [B][128] each, then y, dy [B]
+    int64_t z1 = 0, h1 = 0, z2 = 0, h2 = 0, d1 = 0, d2 = 0, y = 0, dy = 0, acts_total = 0;
+    static MlpLayout acts(int batch) {
+        MlpLayout L{};
+        const int64_t bh = int64_t(batch) * kMlpHid;
+        L.z1 = 0;
+        L.h1 = bh;
+        L.z2 = 2 * bh;
+        L.h2 = 3 * bh;
+        L.d1 = 4 * bh;
+        L.d2 = 5 * bh;
+        L.y = 6 * bh;
+        L.dy = L.y + batch;
+        L.acts_total = L.dy + batch;
+        return L;
+    }
+};
+
+hipError_t launch_tau_features(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, float log_target,
+                               float* out, hipStream_t s);
+// out[0] = smallest norm product >= lo (+inf bits if none), out[1] = largest
+// product, as double bit patterns.
+hipError_t launch_product_bounds(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double lo,
+                                 unsigned long long* out, hipStream_t s);
+// *out = sum of x[q]^2 in FP64; partials holds kSumBlocks doubles.
+hipError_t launch_sumsq(const float* x, int64_t count, double* partials, double* out, hipStream_t s);
+hipError_t launch_mlp_forward(const float* params, const float* x, int batch, float* acts, float* y, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const float* params, const float* x, const float* t, int batch, float* acts,
+                                float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t count, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s);
+
 }  // namespace spamm

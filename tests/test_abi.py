@@ -12,13 +12,15 @@ from pathlib import Path
 import pytest
 
 ROOT = Path(__file__).resolve().parent.parent
-HEADER = ROOT / "include" / "spamm.h"
+HEADERS = sorted((ROOT / "include").glob("*.h"))
 
 
 def _declared():
-    text = HEADER.read_text()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(spamm_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", h.read_text(), flags=re.S)
+        names |= set(re.findall(r"\b(spamm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -35,8 +37,11 @@ def test_header_declares_the_hot_path():
 
 
 def test_every_declared_symbol_is_exported(lib):
+    assert len(HEADERS) >= 2
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
+    for want in ("spamm_search_valid_ratio", "spamm_search_tau_for_error", "spamm_mlp_loss_grad", "spamm_schedule"):
+        assert want in _declared()
 
 
 def test_geometry_queries(lib):
