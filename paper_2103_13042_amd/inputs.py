@@ -151,3 +151,33 @@ def log_uniform_target(index: int, lo: float = 1e-6, hi: float = 1e-2, seed: int
     """Relative-error target of the index-th training pair, log-uniform in [lo, hi)."""
     u = float(uniform01(seed, np.array([index], dtype=np.int64), np.array([0]))[0])
     return float(10.0 ** (np.log10(lo) + u * (np.log10(hi) - np.log10(lo))))
+
+
+def exp_decay_torch(n: int, alpha: float, seed: int, device):
+    """exp_decay(n, alpha, seed) generated with torch on `device` (same counter
+    hash and formula; the integer steps are exact, exp may differ from numpy's
+    in the last FP64 bit).  Returns a float32 [n, n] tensor."""
+    import torch
+
+    def wrap(v: int) -> int:  # uint64 constant as the int64 with the same bits
+        return v - (1 << 64) if v >= 1 << 63 else v
+
+    def lshr(z, s: int):  # logical right shift of int64 bit patterns
+        return (z >> s) & ((1 << (64 - s)) - 1)
+
+    key = wrap(((seed + 1) * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF)
+    m1, m2 = wrap(0xBF58476D1CE4E5B9), wrap(0x94D049BB133111EB)
+    out = torch.empty((n, n), dtype=torch.float32, device=device)
+    cols = torch.arange(n, dtype=torch.int64, device=device)[None, :]
+    step = max(1, (1 << 22) // max(1, n))
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        rows = torch.arange(r0, r1, dtype=torch.int64, device=device)[:, None]
+        z = ((rows << 32) | cols) + key
+        z = (z ^ lshr(z, 30)) * m1
+        z = (z ^ lshr(z, 27)) * m2
+        z = z ^ lshr(z, 31)
+        u = lshr(z, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+        d = (rows - cols).abs().to(torch.float64)
+        out[r0:r1] = (torch.exp(-alpha * d) * (0.5 + 0.5 * u)).to(torch.float32)
+    return out

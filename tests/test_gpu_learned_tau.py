@@ -1,0 +1,68 @@
+"""The learned threshold end to end on the GPU: device-generated training pairs,
+labels from the search, training by the library's kernels, and what the
+trained network gains over the search without it.
+
+Gain bar (held-out pairs): the search seeded with the prediction returns the
+same threshold as the search from scratch (the error grows with tau for these
+non-negative matrices, so both find the largest passing product), needs fewer
+SpAMM evaluations on average, and training cuts the prediction error of the
+untrained network by at least 3x (median |log10 tau_pred - log10 tau|).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2103_13042_amd import binding as sp
+from paper_2103_13042_amd import inputs
+from paper_2103_13042_amd import learned_tau as lt
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+@pytest.mark.parametrize("n,alpha,seed", [(300, 0.05, 3), (1000, 0.3, 1001), (2048, 0.011, 5)])
+def test_device_generator_matches_host_generator(n, alpha, seed):
+    host = inputs.exp_decay(n, alpha, seed).view(np.int32).astype(np.int64)
+    dev = inputs.exp_decay_torch(n, alpha, seed, DEV).cpu().numpy().view(np.int32).astype(np.int64)
+    diff = np.abs(host - dev)
+    # the hash is exact; exp may differ in the last FP64 bit, which moves the
+    # FP32 value by at most one unit, rarely
+    assert diff.max() <= 1 and np.count_nonzero(diff) <= host.size // 10000
+
+
+def test_trained_network_seeds_the_search():
+    n, leaf = 512, 32
+    x, t, recs = lt.generate(430, n, leaf, DEV)
+    assert all(r["err"] <= r["target"] for r in recs)
+    xt, tt, xh, th = x[:400], t[:400], x[400:], t[400:]
+    p0 = torch.from_numpy(inputs.mlp_init(0)).to(DEV)
+    params, hist = lt.train(xt, tt, epochs=150, batch=64, lr=2e-3)
+    assert hist[-1] < 0.2 * hist[0]
+    err_untrained = np.median(np.abs((lt.predict_log10_tau(p0, xh) - th).cpu().numpy()))
+    err_trained = np.median(np.abs((lt.predict_log10_tau(params, xh) - th).cpu().numpy()))
+    assert err_trained * 3 < err_untrained, (err_trained, err_untrained)
+    probs = [lt.decay_problem(n, 400 + q, leaf, DEV) for q in range(30)]
+    rows = lt.compare(params, probs, [inputs.log_uniform_target(400 + q) for q in range(30)])
+    assert all(r["tau"] == r["tau_seeded"] for r in rows)
+    scratch = np.mean([r["evals_scratch"] for r in rows])
+    seeded = np.mean([r["evals_seeded"] for r in rows])
+    assert seeded < scratch, (seeded, scratch)
+
+
+def test_training_is_reproducible():
+    n, leaf = 256, 32
+    x, t, _ = lt.generate(64, n, leaf, DEV)
+    p1, h1 = lt.train(x, t, epochs=5, batch=32)
+    p2, h2 = lt.train(x, t, epochs=5, batch=32)
+    assert torch.equal(p1, p2) and h1 == h2
+
+
+def test_committed_parameters_load():
+    if not lt.PARAMS_FILE.exists():
+        pytest.skip("no trained parameters committed yet")
+    p = lt.load_params(DEV)
+    assert p.numel() == sp.mlp_param_count() and torch.isfinite(p).all()
