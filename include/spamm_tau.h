@@ -70,8 +70,8 @@ spamm_status spamm_mlp_adam(float* params, const float* grad, float* m, float* v
                             float beta1, float beta2, float eps, void* stream);
 
 /* *out (device double) = sum of x[q]^2 over count FP32 values, in FP64 with a
- * fixed reduction order.  scratch: device memory of at least
- * spamm_sumsq_scratch_bytes() bytes. */
+ * fixed reduction order (x may be NULL when count is 0).  scratch: device
+ * memory of at least spamm_sumsq_scratch_bytes() bytes. */
 size_t spamm_sumsq_scratch_bytes(void);
 spamm_status spamm_sumsq(const float* x, int64_t count, double* out, void* scratch, size_t scratch_bytes,
                          void* stream);

@@ -71,6 +71,7 @@ Layout make_layout(const Geom& g) {
     L.mwords = take(sizeof(uint64_t) * nm * 4 * size_t(g.nwords));
     L.mcount = take(sizeof(int32_t) * nm);
     L.mprefix = take(sizeof(int32_t) * (nm + 1));
+    L.mitems = take(sizeof(uint32_t) * nm * size_t(g.bdim));
     L.pairs = take(sizeof(int64_t));
     L.scalars = take(4 * sizeof(double));
     L.partials = take(sizeof(double) * 1024);
@@ -172,7 +173,8 @@ spamm_status enqueue_schedule(const Geom& g, const int32_t* offsets, const int32
     if (g.leaf != 32 && g.leaf != 64) return SPAMM_OK;  // the single-tile kernel reads the plan directly
     const Layout L = make_layout(g);
     return hip_check(spamm::launch_macro_schedule(offsets, klist, g.bdim, at<uint64_t>(ws, L.mwords),
-                                                  at<int32_t>(ws, L.mcount), at<int32_t>(ws, L.mprefix), s),
+                                                  at<int32_t>(ws, L.mcount), at<int32_t>(ws, L.mprefix),
+                                                  at<uint32_t>(ws, L.mitems), s),
                      "macro schedule kernels");
 }
 
@@ -181,7 +183,7 @@ spamm_status enqueue_multiply(const Geom& g, const float* a, const float* b, con
     const bool vec = (g.n % 4) == 0 && aligned16(a) && aligned16(b);
     const Layout L = make_layout(g);
     if (g.leaf == 32 || g.leaf == 64)
-        return hip_check(spamm::launch_macro_multiply(a, b, c, g.n, g.leaf, g.bdim, at<uint64_t>(ws, L.mwords),
+        return hip_check(spamm::launch_macro_multiply(a, b, c, g.n, g.leaf, g.bdim, at<uint32_t>(ws, L.mitems),
                                                       at<int32_t>(ws, L.mprefix), vec, device_cus(), s),
                          "macro multiply kernel");
     return hip_check(spamm::launch_multiply(a, b, c, g.n, g.leaf, g.bdim, offsets, klist,

@@ -169,7 +169,7 @@ size_t spamm_sumsq_scratch_bytes(void) { return sizeof(double) * spamm::kSumBloc
 spamm_status spamm_sumsq(const float* x, int64_t count, double* out, void* scratch, size_t scratch_bytes,
                          void* stream) {
     g_last_error[0] = '\0';
-    if (!x || !out || !scratch) return fail(SPAMM_EINVAL, "null pointer");
+    if ((!x && count > 0) || !out || !scratch) return fail(SPAMM_EINVAL, "null pointer");
     if (count < 0) return fail(SPAMM_EINVAL, "count must be >= 0");
     if (scratch_bytes < spamm_sumsq_scratch_bytes())
         return fail(SPAMM_ENOSPACE, "scratch of %zu bytes, %zu needed", scratch_bytes, spamm_sumsq_scratch_bytes());

@@ -60,14 +60,15 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
                            const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
                            int num_cus, hipStream_t s);
 
-// Multiply on 2x2 macro tiles (leaf 32 and 64), in two launches.  Schedule:
+// Multiply on 2x2 macro tiles (leaf 32 and 64), in two steps.  Schedule:
 // per-macro-tile k bitmaps into words [mb*mb*4*nwords], union sizes into
-// ucount [mb*mb], their exclusive prefix into uprefix [mb*mb + 1].  Multiply:
-// the persistent kernel over that schedule.
+// ucount [mb*mb], their exclusive prefix into uprefix [mb*mb + 1], and the
+// union k lists as packed items into items [<= mb*mb*bdim].  Multiply: the
+// persistent kernel over that schedule.
 hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, uint64_t* words,
-                                 int32_t* ucount, int32_t* uprefix, hipStream_t s);
+                                 int32_t* ucount, int32_t* uprefix, uint32_t* items, hipStream_t s);
 hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
+                                 const uint32_t* items, const int32_t* uprefix, bool vec, int num_cus,
                                  hipStream_t s);
 
 // --------------------------------------------------------------------------

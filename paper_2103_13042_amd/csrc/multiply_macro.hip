@@ -12,9 +12,10 @@
 // Work units: a persistent grid of G workgroups splits the macro tiles into
 // contiguous row-major ranges of equal cost (kUnionCost per union k plus
 // kMacroWrite per macro tile, from the prefix of union sizes), XCD-aware as in
-// the single-tile kernel.  The k-stream is produced from per-tile bitmaps held
-// in global memory and read with scalar loads; the next two items are always
-// known in registers, so tile prefetch never waits on an index load.
+// the single-tile kernel.  The schedule step lists, for every macro tile in
+// order, its union k values with the 4-bit membership of the four tiles
+// (packed items); a workgroup streams its contiguous slice of that list with
+// scalar loads, a few items ahead of the one it multiplies.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -61,6 +62,35 @@ __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restr
     if (lane == 0) ucount[m] = cnt;
 }
 
+// packed pair item: I << 23 | J << 14 | k << 4 | membership (bit a*2+b)
+__device__ __forceinline__ uint32_t mi_pack(uint32_t I, uint32_t J, uint32_t k, uint32_t mem) {
+    return (I << 23) | (J << 14) | (k << 4) | mem;
+}
+
+// One wave per macro tile m: its union k values in ascending order, as packed
+// items at items[uprefix[m] ..].
+__global__ __launch_bounds__(256) void macro_items_kernel(const uint64_t* __restrict__ words,
+                                                          const int32_t* __restrict__ uprefix, int64_t mb, int nw,
+                                                          uint32_t* __restrict__ items) {
+    const int lane = threadIdx.x & 63;
+    const int64_t m = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (m >= mb * mb) return;
+    const uint32_t I = uint32_t(m / mb), J = uint32_t(m - (m / mb) * mb);
+    const uint64_t* wp = words + m * 4 * nw;
+    int64_t base = uprefix[m];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int w = 0; w < nw; ++w) {
+        const uint64_t w0 = wp[w], w1 = wp[nw + w], w2 = wp[2 * nw + w], w3 = wp[3 * nw + w];
+        const uint64_t u = w0 | w1 | w2 | w3;
+        if ((u >> lane) & 1ull) {
+            const uint32_t mem = uint32_t((w0 >> lane) & 1) | uint32_t(((w1 >> lane) & 1) << 1) |
+                                 uint32_t(((w2 >> lane) & 1) << 2) | uint32_t(((w3 >> lane) & 1) << 3);
+            items[base + __popcll(u & below)] = mi_pack(I, J, uint32_t(w) * 64 + lane, mem);
+        }
+        base += __popcll(u);
+    }
+}
+
 template <int LEAF>
 struct MacGeom {
     static constexpr int KC = 32;                 // k per pipeline stage
@@ -77,15 +107,10 @@ struct MacGeom {
     static_assert(NV >= 1 && NV * 4 * kMacThreads == ROWS * KC, "stage split");
 };
 
-// packed pair item: I << 23 | J << 14 | k << 4 | membership (bit a*2+b)
-__device__ __forceinline__ uint32_t mi_pack(uint32_t I, uint32_t J, uint32_t k, uint32_t mem) {
-    return (I << 23) | (J << 14) | (k << 4) | mem;
-}
-
 template <int LEAF, bool VEC>
 __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macro_kernel(
     const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
-    int64_t mb, int nw, const uint64_t* __restrict__ words, const int32_t* __restrict__ uprefix) {
+    int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix) {
     using Gm = MacGeom<LEAF>;
     __shared__ __attribute__((aligned(16))) float lds[2 * Gm::STAGE];
 
@@ -115,31 +140,15 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
     if (m_begin >= m_end) return;
     const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]) * Gm::NCH;
 
-    // producer of the union k-stream (wave-uniform state)
-    int64_t pm = m_begin;
-    int pw = -1;
-    uint64_t prem = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    // this group's slice of the item list (wave-uniform); past the end the
+    // last item repeats (a harmless reload)
+    const uint32_t* ip = items + uprefix[m_begin];
+    const int64_t npairs = int64_t(uprefix[m_end] - uprefix[m_begin]);
+    int64_t pp = 0;
     uint32_t last = 0;
     auto produce = [&]() -> uint32_t {
-        while (prem == 0) {
-            if (++pw == nw) {
-                pw = 0;
-                ++pm;
-            }
-            if (pm >= m_end) return last;  // past the end: repeat the last item (a harmless reload)
-            const uint64_t* wp = words + pm * 4 * nw + pw;
-            w0 = wp[0];
-            w1 = wp[nw];
-            w2 = wp[2 * nw];
-            w3 = wp[3 * nw];
-            prem = w0 | w1 | w2 | w3;
-        }
-        const uint32_t bit = uint32_t(__builtin_ctzll(prem));
-        prem &= prem - 1;
-        const uint32_t mem = uint32_t((w0 >> bit) & 1) | uint32_t(((w1 >> bit) & 1) << 1) |
-                             uint32_t(((w2 >> bit) & 1) << 2) | uint32_t(((w3 >> bit) & 1) << 3);
-        const uint32_t I = uint32_t(pm / mb), J = uint32_t(pm - (pm / mb) * mb);
-        last = mi_pack(I, J, uint32_t(pw) * 64 + bit, mem);
+        if (pp < npairs) last = ip[pp];
+        ++pp;
         return last;
     };
 
@@ -309,11 +318,11 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
 // straight into LDS (global_load_lds_dwordx4) through four LDS stages, so three
 // items are in flight while one is multiplied and no registers stage the data.
 //
-// Sixteen waves: wave w computes the 32x32 quadrant (w >> 1 & 1, w & 1) of
-// output tile w >> 2 of the macro tile.  Waves are dealt to the four SIMDs
-// round-robin, so each output tile has one wave on every SIMD and the MFMA
-// load of an item is the same on all SIMDs whichever of the four tiles keep
-// its k.
+// Sixteen waves: wave w computes the 32x32 quadrant (w >> 3 & 1, w >> 2 & 1)
+// of output tile (w + (w >> 2)) & 3 of the macro tile.  Waves are dealt to the
+// four SIMDs round-robin (w, w+4, w+8, w+12 on one SIMD), so each output tile
+// has one wave on every SIMD and the MFMA load of an item is the same on all
+// SIMDs whichever of the four tiles keep its k.
 //
 // LDS rows are stored without padding; 16-byte chunks are XOR-swizzled so the
 // MFMA operand reads are free of bank conflicts: A row r keeps global chunk c
@@ -328,7 +337,7 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
 constexpr int kDmaThreads = 1024;
 constexpr int kDmaStores = 16;  // per wave per macro tile
 #ifndef SPAMM_DMA_KC
-#define SPAMM_DMA_KC 32
+#define SPAMM_DMA_KC 64
 #endif
 #ifndef SPAMM_DMA_STAGES
 #define SPAMM_DMA_STAGES 2
@@ -360,14 +369,19 @@ __device__ __forceinline__ void wait_copies(int stores) {
 
 __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
-    int64_t mb, int nw, const uint64_t* __restrict__ words, const int32_t* __restrict__ uprefix) {
+    int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix) {
     constexpr int LEAF = 64, KC = kDmaKC, NCH = LEAF / KC, SPC = KC / 2;
     constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;  // 16 KiB each
     constexpr int STAGE_BYTES = ABYTES + BBYTES;
     __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = wave >> 2, wa = tile >> 1, wb = tile & 1, qr = (wave >> 1) & 1, qc = wave & 1;
+    // waves w, w+4, w+8, w+12 share a SIMD: give them different output tiles
+    // (and each tile one wave per quadrant), so every SIMD holds one wave of
+    // each tile and the MFMA work of an item is spread evenly whichever tiles
+    // keep its k
+    const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
+              qc = (wave >> 2) & 1;
     const int ir = lane & 31, g = lane >> 5;
 
     const int64_t groups = gridDim.x;
@@ -391,30 +405,15 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     if (m_begin >= m_end) return;
     const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]) * NCH;
 
-    int64_t pm = m_begin;
-    int pw = -1;
-    uint64_t prem = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    // this group's slice of the item list (wave-uniform); past the end the
+    // last item repeats (a harmless reload)
+    const uint32_t* ip = items + uprefix[m_begin];
+    const int64_t npairs = int64_t(uprefix[m_end] - uprefix[m_begin]);
+    int64_t pp = 0;
     uint32_t last = 0;
     auto produce = [&]() -> uint32_t {
-        while (prem == 0) {
-            if (++pw == nw) {
-                pw = 0;
-                ++pm;
-            }
-            if (pm >= m_end) return last;
-            const uint64_t* wp = words + pm * 4 * nw + pw;
-            w0 = wp[0];
-            w1 = wp[nw];
-            w2 = wp[2 * nw];
-            w3 = wp[3 * nw];
-            prem = w0 | w1 | w2 | w3;
-        }
-        const uint32_t bit = uint32_t(__builtin_ctzll(prem));
-        prem &= prem - 1;
-        const uint32_t mem = uint32_t((w0 >> bit) & 1) | uint32_t(((w1 >> bit) & 1) << 1) |
-                             uint32_t(((w2 >> bit) & 1) << 2) | uint32_t(((w3 >> bit) & 1) << 3);
-        const uint32_t I = uint32_t(pm / mb), J = uint32_t(pm - (pm / mb) * mb);
-        last = mi_pack(I, J, uint32_t(pw) * 64 + bit, mem);
+        if (pp < npairs) last = ip[pp];
+        ++pp;
         return last;
     };
 
@@ -458,22 +457,38 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
                                              16, 0, 0);
         }
     };
+    // operands are read in groups of GRP MFMA steps, one group ahead of the
+    // MFMAs that use them, so the LDS latency hides behind MFMA work
+    constexpr int GRP = 8, NGRP = SPC / GRP;
+    static_assert(SPC % GRP == 0, "operand groups");
     auto compute = [&](int st) {
         const char* sa = lds + st * STAGE_BYTES;
         const char* sb = sa + ABYTES;
         const int r = wa * 64 + qr * 32 + ir;
         const int cc = wb * 64 + qc * 32 + ir;
         const char* brow = sb + ((cc >> 2) ^ (8 * g)) * 16 + (cc & 3) * 4;
+        f4 av[2][GRP / 4];
+        float bv[2][GRP];
+        auto load = [&](int grp, int buf) {
 #pragma unroll
-        for (int q = 0; q < SPC / 4; ++q) {
-            const int c = (g * (SPC / 4) + q) ^ aswz(r);
-            const f4 av = *reinterpret_cast<const f4*>(sa + r * (KC * 4) + c * 16);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int kr = g * SPC + 4 * q + u;
-                const float bv = *reinterpret_cast<const float*>(brow + kr * (2 * LEAF * 4));
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv, acc, 0, 0, 0);
+            for (int q = 0; q < GRP / 4; ++q) {
+                const int c = (g * (SPC / 4) + grp * (GRP / 4) + q) ^ aswz(r);
+                av[buf][q] = *reinterpret_cast<const f4*>(sa + r * (KC * 4) + c * 16);
             }
+#pragma unroll
+            for (int u = 0; u < GRP; ++u) {
+                const int kr = g * SPC + grp * GRP + u;
+                bv[buf][u] = *reinterpret_cast<const float*>(brow + kr * (2 * LEAF * 4));
+            }
+        };
+        load(0, 0);
+#pragma unroll
+        for (int grp = 0; grp < NGRP; ++grp) {
+            if (grp + 1 < NGRP) load(grp + 1, (grp + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);  // keep the next group's reads ahead of these MFMAs
+#pragma unroll
+            for (int u = 0; u < GRP; ++u)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[grp & 1][u >> 2][u & 3], bv[grp & 1][u], acc, 0, 0, 0);
         }
     };
 
@@ -538,27 +553,29 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
 }
 
 hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, uint64_t* words,
-                                 int32_t* ucount, int32_t* uprefix, hipStream_t s) {
+                                 int32_t* ucount, int32_t* uprefix, uint32_t* items, hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int nw = int((bdim + 63) / 64);
     macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, words, ucount);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_plan_scan(ucount, nm, uprefix, uprefix, nm, nullptr, s);
+    e = launch_plan_scan(ucount, nm, uprefix, uprefix, nm, nullptr, s);
+    if (e != hipSuccess) return e;
+    macro_items_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(words, uprefix, mb, nw, items);
+    return hipGetLastError();
 }
 
 template <int LEAF>
 static hipError_t launch_macro_run(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
-                                   const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
+                                   const uint32_t* items, const int32_t* uprefix, bool vec, int num_cus,
                                    hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
-    const int nw = int((bdim + 63) / 64);
     const int64_t cap = ((nm + 7) / 8) * 8;
     if (LEAF == 64 && vec && n % 128 == 0) {
         int64_t groups = int64_t(num_cus);
         if (groups > cap) groups = cap;
         groups = ((groups + 7) / 8) * 8;
-        multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, bdim, mb, nw, words, uprefix);
+        multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, bdim, mb, items, uprefix);
         return hipGetLastError();
     }
     int64_t groups = int64_t(num_cus) * MacGeom<LEAF>::OCC;
@@ -566,19 +583,19 @@ static hipError_t launch_macro_run(const float* a, const float* b, float* c, int
     groups = ((groups + 7) / 8) * 8;
     if (vec)
         multiply_macro_kernel<LEAF, true>
-            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, nw, words, uprefix);
+            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, items, uprefix);
     else
         multiply_macro_kernel<LEAF, false>
-            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, nw, words, uprefix);
+            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, items, uprefix);
     return hipGetLastError();
 }
 
 hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const uint64_t* words, const int32_t* uprefix, bool vec, int num_cus,
+                                 const uint32_t* items, const int32_t* uprefix, bool vec, int num_cus,
                                  hipStream_t s) {
     switch (leaf) {
-        case 32: return launch_macro_run<32>(a, b, c, n, bdim, words, uprefix, vec, num_cus, s);
-        case 64: return launch_macro_run<64>(a, b, c, n, bdim, words, uprefix, vec, num_cus, s);
+        case 32: return launch_macro_run<32>(a, b, c, n, bdim, items, uprefix, vec, num_cus, s);
+        case 64: return launch_macro_run<64>(a, b, c, n, bdim, items, uprefix, vec, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }
