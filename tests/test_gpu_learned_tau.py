@@ -61,8 +61,18 @@ def test_training_is_reproducible():
     assert torch.equal(p1, p2) and h1 == h2
 
 
-def test_committed_parameters_load():
-    if not lt.PARAMS_FILE.exists():
-        pytest.skip("no trained parameters committed yet")
+def test_committed_network_cuts_search_evaluations():
+    # the network trained on 10,000 N=2048 pairs (paper_2103_13042_amd/data),
+    # on pairs it has not seen: same thresholds, at least 20 % fewer SpAMM
+    # evaluations, and predictions within a factor 2 (median)
     p = lt.load_params(DEV)
     assert p.numel() == sp.mlp_param_count() and torch.isfinite(p).all()
+    n, leaf = 2048, 64
+    idx = [50000 + q for q in range(16)]
+    probs = [lt.decay_problem(n, i, leaf, DEV) for i in idx]
+    rows = lt.compare(p, probs, [inputs.log_uniform_target(i) for i in idx])
+    assert all(r["tau"] == r["tau_seeded"] for r in rows)
+    scratch = np.mean([r["evals_scratch"] for r in rows])
+    seeded = np.mean([r["evals_seeded"] for r in rows])
+    assert seeded < 0.8 * scratch, (seeded, scratch)
+    assert np.median([abs(r["log10_ratio_pred"]) for r in rows]) < np.log10(2.0)
