@@ -148,6 +148,50 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
 spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,
                             int64_t* pairs, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Reduced-precision leaf products.  The skip mask is that of the FP32 inputs
+ * (norms, pyramid and plan as above); only the leaf products change, as the
+ * paper's FP16 tensor-core variant does (Algorithm 3, section 3.3):
+ *   SPAMM_PREC_BF16   every element of A and B rounded to bfloat16 (nearest,
+ *                     ties to even); FP32 accumulation of the exact products.
+ *   SPAMM_PREC_F16X3  per matrix a power-of-two scale s = 2^(15 - ceil(log2 M)),
+ *                     M its largest leaf-tile norm; hi = fp16(s x),
+ *                     lo = fp16(s x - hi); per leaf product hi*hi + hi*lo +
+ *                     lo*hi accumulated in FP32, scaled by 1/(sA sB) when stored.
+ * Supported for leaf 64 and n a multiple of 128 (EUNSUPPORTED otherwise). */
+#define SPAMM_PREC_FP32 0
+#define SPAMM_PREC_BF16 1
+#define SPAMM_PREC_F16X3 2
+
+/* Bytes of the split operands of A and B for a precision (0 for FP32 or bad
+ * arguments): a 256-byte header (the two scale exponents), then n*n halves per
+ * plane: A (row-major), [A lo], B transposed, [B lo transposed]. */
+size_t spamm_split_bytes(int64_t n, int32_t precision);
+
+/* Write the split operands of A and B into `split` (device, 256-byte aligned,
+ * spamm_split_bytes bytes).  pyr_a, pyr_b: their pyramids (spamm_pyramid or
+ * spamm_prepare's workspace copies), used for the f16x3 scales.  EINVAL: null
+ * pointer, misalignment (a and b 16 bytes), overlap with a or b, precision not
+ * BF16/F16X3; ENOSPACE: split too small. */
+spamm_status spamm_split(const float* a, const float* b, int64_t n, int32_t leaf, int32_t precision,
+                         const double* pyr_a, const double* pyr_b, void* split, size_t split_bytes, void* stream);
+
+/* spamm_execute with reduced-precision products from split operands:
+ * spamm_execute_split = spamm_schedule + spamm_execute_split_scheduled (the
+ * multiply kernel alone, after spamm_schedule on the same plan and workspace). */
+spamm_status spamm_execute_split(const void* split, int64_t n, int32_t leaf, int32_t precision,
+                                 const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+spamm_status spamm_execute_split_scheduled(const void* split, int64_t n, int32_t leaf, int32_t precision,
+                                           const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
+                                           size_t workspace_bytes, void* stream);
+
+/* The whole path with reduced-precision products: spamm_prepare, spamm_split,
+ * spamm_execute_split.  SPAMM_PREC_FP32 is spamm_multiply (split unused, may be
+ * NULL).  Errors as spamm_multiply and spamm_split. */
+spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                      int32_t precision, float* c, int64_t* pairs, void* split, size_t split_bytes,
+                                      void* workspace, size_t workspace_bytes, void* stream);
+
 /* The valid-ratio search of section 3.5.2: the threshold tau whose valid
  * ratio (kept leaf triples / bdim^3) is within tol of target.  ave is the
  * mean of the norm products over all bdim^3 triples; tau starts at ave; while

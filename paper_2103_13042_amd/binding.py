@@ -52,6 +52,11 @@ _SIGS = {
     "spamm_error_for_tau": (_st, [_vp, _vp, _i64, _i32, _f64, _vp, _vp, _f64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_search_tau_for_error": (
         _st, [_vp, _vp, _i64, _i32, _f64, _f64, _i32, _vp, _vp, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_split_bytes": (_sz, [_i64, _i32]),
+    "spamm_split": (_st, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_execute_split": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_execute_split_scheduled": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_multiply_precision": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_strerror": (ctypes.c_char_p, [_st]),
     "spamm_last_error": (ctypes.c_char_p, []),
 }
@@ -426,3 +431,84 @@ def search_tau_for_error(a, b, leaf: int, target: float, pyr_a, pyr_b, ab_sumsq:
         float(ab_sumsq), _ptr(e), ctypes.byref(tau), ctypes.byref(err), ctypes.byref(pairs), ctypes.byref(evals),
         _ptr(ws), ws.numel(), _stream(a.device)), "spamm_search_tau_for_error")
     return tau.value, err.value, pairs.value, evals.value
+
+
+# -- reduced-precision leaf products -----------------------------------------
+
+PRECISIONS = {"fp32": 0, "bf16": 1, "f16x3": 2}
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, str):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        return PRECISIONS[precision]
+    return int(precision)
+
+
+def split_bytes(n: int, precision) -> int:
+    return int(_lib.spamm_split_bytes(n, _prec(precision)))
+
+
+def split_buffer(n: int, precision, device) -> torch.Tensor:
+    """A device buffer for the split operands (torch allocations are 256-byte aligned)."""
+    nb = split_bytes(n, precision)
+    if nb == 0:
+        raise ValueError("no split operands for this precision")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def split_views(buf: torch.Tensor, n: int, precision):
+    """(exps int32 [2], planes: list of int16 [n, n] views: A hi, [A lo], Bt hi, [Bt lo])."""
+    p = _prec(precision)
+    exps = buf[:8].view(torch.int32)
+    plane = (n * n * 2 + 255) // 256 * 256
+    count = 4 if p == 2 else 2
+    planes = [buf[256 + q * plane : 256 + q * plane + n * n * 2].view(torch.int16).view(n, n) for q in range(count)]
+    return exps, planes
+
+
+def split(a, b, leaf: int, precision, pyr_a, pyr_b, *, out=None) -> torch.Tensor:
+    """Split operands of A and B (spamm_split)."""
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    out = split_buffer(n, precision, a.device) if out is None else out
+    _check(_lib.spamm_split(_ptr(a), _ptr(b), n, leaf, _prec(precision), _ptr(pyr_a), _ptr(pyr_b), _ptr(out),
+                            out.numel(), _stream(a.device)), "spamm_split")
+    return out
+
+
+def execute_split(split_buf, n: int, leaf: int, precision, offsets, klist, *, c=None, ws=None,
+                  scheduled: bool = False) -> torch.Tensor:
+    """Reduced-precision multiply of a plan (spamm_execute_split, or with
+    scheduled=True spamm_execute_split_scheduled after schedule())."""
+    dev = split_buf.device
+    _check_plan(offsets, klist, n, leaf, dev)
+    c = torch.empty((n, n), dtype=torch.float32, device=dev) if c is None else c
+    if _square_f32(c, "c") != n:
+        raise ValueError("c must be n x n")
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    fn = _lib.spamm_execute_split_scheduled if scheduled else _lib.spamm_execute_split
+    _check(fn(_ptr(split_buf), n, leaf, _prec(precision), _ptr(offsets), _ptr(klist), _ptr(c), _ptr(ws), ws.numel(),
+              _stream(dev)), "spamm_execute_split")
+    return c
+
+
+def multiply_precision(a, b, tau: float, leaf: int, precision, *, c=None, pairs=None, split_buf=None, ws=None,
+                       sync: bool = True):
+    """The whole path with reduced-precision products (spamm_multiply_precision): (C, pairs)."""
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    dev = a.device
+    p = _prec(precision)
+    c = torch.empty_like(a) if c is None else c
+    pairs = torch.empty(1, dtype=torch.int64, device=dev) if pairs is None else pairs
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    if split_buf is None and p != 0:
+        split_buf = split_buffer(n, p, dev)
+    _check(_lib.spamm_multiply_precision(_ptr(a), _ptr(b), n, float(tau), leaf, p, _ptr(c), _ptr(pairs),
+                                         _ptr(split_buf), split_buf.numel() if split_buf is not None else 0,
+                                         _ptr(ws), ws.numel(), _stream(dev)), "spamm_multiply_precision")
+    return (c, int(pairs.item())) if sync else (c, pairs)

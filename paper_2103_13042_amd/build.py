@@ -18,8 +18,8 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 LIB = PKG / "libspamm.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "learned.hip", CSRC / "api.hip",
-           CSRC / "api_tau.hip"]
+SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "split.hip", CSRC / "learned.hip",
+           CSRC / "api.hip", CSRC / "api_tau.hip"]
 ARCH = "gfx950"
 
 

@@ -198,6 +198,38 @@ spamm_status enqueue_execute(const Geom& g, const float* a, const float* b, cons
     return enqueue_multiply(g, a, b, offsets, klist, c, ws, s);
 }
 
+namespace {
+size_t plane_bytes(int64_t n) { return (size_t(n) * size_t(n) * 2 + 255) / 256 * 256; }
+int split_planes(int32_t precision) { return precision == spamm::kPrecF16x3 ? 4 : 2; }
+
+spamm::SplitLayout split_layout(void* split, int64_t n, int32_t precision) {
+    char* base = static_cast<char*>(split);
+    const size_t pb = plane_bytes(n);
+    spamm::SplitLayout L{};
+    L.exps = reinterpret_cast<int32_t*>(base);
+    char* p = base + 256;
+    auto next = [&]() {
+        uint16_t* q = reinterpret_cast<uint16_t*>(p);
+        p += pb;
+        return q;
+    };
+    L.a_hi = next();
+    L.a_lo = precision == spamm::kPrecF16x3 ? next() : nullptr;
+    L.bt_hi = next();
+    L.bt_lo = precision == spamm::kPrecF16x3 ? next() : nullptr;
+    return L;
+}
+}  // namespace
+
+spamm_status check_lowp(const Geom& g, int32_t precision) {
+    if (precision != spamm::kPrecBf16 && precision != spamm::kPrecF16x3)
+        return fail(SPAMM_EINVAL, "precision %d is not a reduced-precision form (1: bf16, 2: f16x3)", precision);
+    if (g.leaf != 64 || g.n % 128 != 0)
+        return fail(SPAMM_EUNSUPPORTED, "reduced-precision products need leaf 64 and n a multiple of 128 (n=%lld "
+                    "leaf=%d)", (long long)g.n, g.leaf);
+    return check_grid(g);
+}
+
 }  // namespace spamm_host
 
 using namespace spamm_host;
@@ -356,6 +388,88 @@ spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double ta
                        stream);
     if (st != SPAMM_OK) return st;
     return spamm_execute(a, b, n, leaf, offsets, klist, c, workspace, workspace_bytes, stream);
+}
+
+size_t spamm_split_bytes(int64_t n, int32_t precision) {
+    if (n <= 0 || (precision != spamm::kPrecBf16 && precision != spamm::kPrecF16x3)) return 0;
+    return 256 + size_t(split_planes(precision)) * plane_bytes(n);
+}
+
+spamm_status spamm_split(const float* a, const float* b, int64_t n, int32_t leaf, int32_t precision,
+                         const double* pyr_a, const double* pyr_b, void* split, size_t split_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!a || !b || !pyr_a || !pyr_b || !split) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_lowp(g, precision);
+    if (st != SPAMM_OK) return st;
+    if (!aligned16(a) || !aligned16(b) || (reinterpret_cast<uintptr_t>(split) & 255u) != 0)
+        return fail(SPAMM_EINVAL, "a, b need 16-byte and split 256-byte alignment");
+    if (split_bytes < spamm_split_bytes(n, precision))
+        return fail(SPAMM_ENOSPACE, "split buffer of %zu bytes, %zu needed", split_bytes,
+                    spamm_split_bytes(n, precision));
+    const size_t sb = spamm_split_bytes(n, precision);
+    const size_t mb = sizeof(float) * size_t(n) * size_t(n);
+    if (overlaps(split, sb, a, mb) || overlaps(split, sb, b, mb))
+        return fail(SPAMM_EINVAL, "split buffer overlaps a or b");
+    return hip_check(spamm::launch_split(a, b, n, g.bdim, g.lv, pyr_a, pyr_b, precision,
+                                         split_layout(split, n, precision), static_cast<hipStream_t>(stream)),
+                     "split kernels");
+}
+
+spamm_status spamm_execute_split_scheduled(const void* split, int64_t n, int32_t leaf, int32_t precision,
+                                           const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
+                                           size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!split || !offsets || !klist || !c) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_lowp(g, precision);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    if (overlaps(c, sizeof(float) * size_t(n) * size_t(n), split, spamm_split_bytes(n, precision)))
+        return fail(SPAMM_EINVAL, "c overlaps the split buffer");
+    const Layout L = make_layout(g);
+    return hip_check(spamm::launch_lowp_multiply(split_layout(const_cast<void*>(split), n, precision), c, n, g.bdim,
+                                                 precision, at<uint32_t>(workspace, L.mitems),
+                                                 at<int32_t>(workspace, L.mprefix), device_cus(),
+                                                 static_cast<hipStream_t>(stream)),
+                     "reduced-precision multiply kernel");
+}
+
+spamm_status spamm_execute_split(const void* split, int64_t n, int32_t leaf, int32_t precision,
+                                 const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+    spamm_status st = spamm_schedule(offsets, klist, n, leaf, workspace, workspace_bytes, stream);
+    if (st != SPAMM_OK) return st;
+    return spamm_execute_split_scheduled(split, n, leaf, precision, offsets, klist, c, workspace, workspace_bytes,
+                                         stream);
+}
+
+spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                      int32_t precision, float* c, int64_t* pairs, void* split, size_t split_bytes,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    if (precision == spamm::kPrecFp32)
+        return spamm_multiply(a, b, n, tau, leaf, c, pairs, workspace, workspace_bytes, stream);
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_mul_args(g, a, b, c);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_lowp(g, precision)) != SPAMM_OK) return st;
+    if ((st = check_tau(tau)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    const Layout L = make_layout(g);
+    int32_t* offsets = at<int32_t>(workspace, L.offsets);
+    int32_t* klist = at<int32_t>(workspace, L.klist);
+    int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
+    st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
+                       stream);
+    if (st != SPAMM_OK) return st;
+    st = spamm_split(a, b, n, leaf, precision, at<double>(workspace, L.pyr[0]), at<double>(workspace, L.pyr[1]),
+                     split, split_bytes, stream);
+    if (st != SPAMM_OK) return st;
+    return spamm_execute_split(split, n, leaf, precision, offsets, klist, c, workspace, workspace_bytes, stream);
 }
 
 spamm_status spamm_search_valid_ratio(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf,

@@ -119,4 +119,22 @@ hipError_t launch_mlp_loss_grad(const float* params, const float* x, const float
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int64_t count, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t s);
 
+// --------------------------------------------------------------------------
+// Reduced-precision leaf products (split.hip, multiply_macro.hip).
+
+constexpr int kPrecFp32 = 0, kPrecBf16 = 1, kPrecF16x3 = 2;
+
+// Device pointers into a split buffer: scale exponents [2] (A, B), A planes
+// (row-major, n x n halves), Bt planes (B transposed, n x n halves); the lo
+// planes are used by f16x3 only.
+struct SplitLayout {
+    int32_t* exps;
+    uint16_t *a_hi, *a_lo, *bt_hi, *bt_lo;
+};
+
+hipError_t launch_split(const float* a, const float* b, int64_t n, int64_t bdim, int lv, const double* pyr_a,
+                        const double* pyr_b, int precision, const SplitLayout& L, hipStream_t s);
+hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64_t bdim, int precision,
+                                const uint32_t* items, const int32_t* uprefix, int num_cus, hipStream_t s);
+
 }  // namespace spamm

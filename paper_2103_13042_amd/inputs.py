@@ -153,11 +153,8 @@ def log_uniform_target(index: int, lo: float = 1e-6, hi: float = 1e-2, seed: int
     return float(10.0 ** (np.log10(lo) + u * (np.log10(hi) - np.log10(lo))))
 
 
-def exp_decay_torch(n: int, alpha: float, seed: int, device):
-    """exp_decay(n, alpha, seed) generated with torch on `device` (same counter
-    hash and formula; the integer steps are exact, exp may differ from numpy's
-    in the last FP64 bit).  Returns a float32 [n, n] tensor."""
-    import torch
+def _uniform01_torch(seed: int, rows, cols):
+    """uniform01 with torch int64 tensors (same bits as the numpy version)."""
 
     def wrap(v: int) -> int:  # uint64 constant as the int64 with the same bits
         return v - (1 << 64) if v >= 1 << 63 else v
@@ -167,17 +164,65 @@ def exp_decay_torch(n: int, alpha: float, seed: int, device):
 
     key = wrap(((seed + 1) * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF)
     m1, m2 = wrap(0xBF58476D1CE4E5B9), wrap(0x94D049BB133111EB)
+    z = ((rows << 32) | cols) + key
+    z = (z ^ lshr(z, 30)) * m1
+    z = (z ^ lshr(z, 27)) * m2
+    z = z ^ lshr(z, 31)
+    import torch
+
+    return lshr(z, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+
+
+def _build_torch(n: int, device, fn):
+    import torch
+
     out = torch.empty((n, n), dtype=torch.float32, device=device)
     cols = torch.arange(n, dtype=torch.int64, device=device)[None, :]
     step = max(1, (1 << 22) // max(1, n))
     for r0 in range(0, n, step):
         r1 = min(n, r0 + step)
         rows = torch.arange(r0, r1, dtype=torch.int64, device=device)[:, None]
-        z = ((rows << 32) | cols) + key
-        z = (z ^ lshr(z, 30)) * m1
-        z = (z ^ lshr(z, 27)) * m2
-        z = z ^ lshr(z, 31)
-        u = lshr(z, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
-        d = (rows - cols).abs().to(torch.float64)
-        out[r0:r1] = (torch.exp(-alpha * d) * (0.5 + 0.5 * u)).to(torch.float32)
+        out[r0:r1] = fn(rows, cols).to(torch.float32)
     return out
+
+
+def exp_decay_torch(n: int, alpha: float, seed: int, device):
+    """exp_decay(n, alpha, seed) generated with torch on `device` (same counter
+    hash and formula; the integer steps are exact, exp may differ from numpy's
+    in the last FP64 bit).  Returns a float32 [n, n] tensor."""
+    import torch
+
+    return _build_torch(n, device, lambda r, c: torch.exp(-alpha * (r - c).abs().to(torch.float64))
+                        * (0.5 + 0.5 * _uniform01_torch(seed, r, c)))
+
+
+# ReLU-like matrices: 60 % exact zeros at random positions, the other entries
+# N(0, 1) (Box-Muller from two more uniforms) clipped at 0.  Three independent
+# streams per element: seeds 4s (zero mask), 4s+1 and 4s+2 (Box-Muller).
+RELU_ZERO_FRACTION = 0.6
+
+
+def relu_like(n: int, seed: int) -> np.ndarray:
+    def fn(r, c, d):
+        keep = uniform01(4 * seed, r, c) >= RELU_ZERO_FRACTION
+        u1 = 1.0 - uniform01(4 * seed + 1, r, c)  # (0, 1]
+        u2 = uniform01(4 * seed + 2, r, c)
+        z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+        return np.where(keep, np.maximum(z, 0.0), 0.0)
+
+    return _build(n, fn)
+
+
+def relu_like_torch(n: int, seed: int, device):
+    """relu_like on `device` (log, sqrt and cos may differ from numpy's in the
+    last FP64 bit)."""
+    import torch
+
+    def fn(r, c):
+        keep = _uniform01_torch(4 * seed, r, c) >= RELU_ZERO_FRACTION
+        u1 = 1.0 - _uniform01_torch(4 * seed + 1, r, c)
+        u2 = _uniform01_torch(4 * seed + 2, r, c)
+        z = torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * np.pi * u2)
+        return torch.where(keep, z.clamp_min(0.0), torch.zeros_like(z))
+
+    return _build_torch(n, device, fn)

@@ -1,0 +1,186 @@
+"""Reduced-precision leaf products on the GPU (through the C ABI) against the
+FP64 oracle of oracle/precision.py.
+
+Bars:
+  - split operands: bitwise equal to the oracle's rounding (bf16; FP16 hi and
+    lo with the same scale exponents), B planes transposed;
+  - skip mask / pairs: identical to the FP32 path's;
+  - C: every element within gamma_K * (|A||B| restricted to the kept pairs)
+    * (1 + 2^-7) of the oracle's reduced-precision result, with K the number
+    of FP32 accumulations per element (n for bf16, 3n for the three FP16
+    products), i.e. only the FP32 accumulation differs;
+  - and, stated as the accuracy of each form against the FP64 SpAMM oracle of
+    the FP32 inputs: relative Frobenius error <= 1e-6 for f16x3 and <= 1e-2
+    for bf16 (measured values printed).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import precision as pr
+from paper_2103_13042_amd import binding as sp
+from paper_2103_13042_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+U32 = 2.0**-24
+
+
+def gpu(x: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def gamma(k: int) -> float:
+    return k * U32 / (1.0 - k * U32)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16x3"])
+@pytest.mark.parametrize("n", [256, 1024])
+def test_split_operands_match_oracle(precision, n):
+    a, b = inputs.exp_decay(n, 0.05, 11), inputs.algebraic_decay_signed(n, 12)
+    ga, gb = gpu(a), gpu(b)
+    pa, pb = sp.pyramid(ga, 64), sp.pyramid(gb, 64)
+    buf = sp.split(ga, gb, 64, precision, pa, pb)
+    exps, planes = sp.split_views(buf, n, precision)
+    planes = [p.cpu().numpy().view(np.float16).astype(np.float32) if precision == "f16x3"
+              else (p.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32) for p in planes]
+    if precision == "bf16":
+        assert np.array_equal(planes[0], pr.bf16_round(a))
+        assert np.array_equal(planes[1], pr.bf16_round(b).T)
+    else:
+        ea, eb = (pr.f16_scale_exponent(pr.max_leaf_norm(x, 64)) for x in (a, b))
+        assert exps.cpu().tolist() == [ea, eb]
+        ha, la = pr.f16_split(a, ea)
+        hb, lb = pr.f16_split(b, eb)
+        for got, want in zip(planes, (ha, la, hb.T, lb.T)):
+            assert np.array_equal(got, want)
+
+
+def _check(c_gpu, a, b, tau, leaf, precision):
+    n = a.shape[0]
+    c_or, pairs = pr.spamm_precision(a, b, tau, leaf, precision)
+    abs_ref, _, _ = oracle.spamm(np.abs(a), np.abs(b), tau, leaf)
+    k = n if precision == "bf16" else 3 * n
+    err = np.abs(c_gpu.astype(np.float64) - c_or)
+    assert np.all(err <= gamma(k) * abs_ref * (1 + 2.0**-7) + 1e-300), float(np.max(err - gamma(k) * abs_ref))
+    c64, _, _ = oracle.spamm(a, b, tau, leaf)
+    rel = float(np.linalg.norm(c_gpu.astype(np.float64) - c64) / np.linalg.norm(c64))
+    print(f"{precision} n={n} tau={tau:g}: rel. Frobenius error vs the FP64 SpAMM oracle {rel:.2e}")
+    assert rel <= (1e-6 if precision == "f16x3" else 1e-2)
+    return pairs
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16x3"])
+@pytest.mark.parametrize("n,kind,tau", [(1024, "exp", 1e-6), (2048, "alg", 1e-6), (256, "exp", 0.0),
+                                        (768, "relu", 1e-6), (1024, "alg", 1e-3)])
+def test_multiply_precision_matches_oracle(precision, n, kind, tau):
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.05, 0), inputs.exp_decay(n, 0.05, 1)
+    elif kind == "alg":
+        a, b = inputs.algebraic_decay_signed(n, 0), inputs.algebraic_decay_signed(n, 1)
+    else:
+        a, b = inputs.relu_like(n, 0), inputs.relu_like(n, 1)
+    c, pairs = sp.multiply_precision(gpu(a), gpu(b), tau, 64, precision)
+    _, pairs32 = sp.multiply(gpu(a), gpu(b), tau, 64)
+    assert pairs == pairs32
+    assert _check(c.cpu().numpy(), a, b, tau, 64, precision) == pairs
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16x3"])
+def test_staged_split_path_equals_fused(precision):
+    n, leaf, tau = 1024, 64, 1e-6
+    a, b = inputs.exp_decay(n, 0.02, 5), inputs.exp_decay(n, 0.02, 6)
+    ga, gb = gpu(a), gpu(b)
+    c_fused, _ = sp.multiply_precision(ga, gb, tau, leaf, precision)
+    ws = sp.workspace(n, leaf, DEV)
+    offsets, klist, _ = sp.prepare(ga, gb, tau, leaf, ws=ws)
+    pa, pb = sp.pyramid(ga, leaf), sp.pyramid(gb, leaf)
+    buf = sp.split(ga, gb, leaf, precision, pa, pb)
+    c1 = sp.execute_split(buf, n, leaf, precision, offsets, klist, ws=ws)
+    sp.schedule(offsets, klist, n, leaf, ws=ws)
+    c2 = sp.execute_split(buf, n, leaf, precision, offsets, klist, ws=ws, scheduled=True)
+    assert torch.equal(c_fused, c1) and torch.equal(c1, c2)
+
+
+def test_zero_and_tau_above_every_product():
+    n = 512
+    z = torch.zeros(n, n, device=DEV)
+    c, pairs = sp.multiply_precision(z, z, 0.0, 64, "f16x3")
+    assert pairs == (n // 64) ** 3 and int(torch.count_nonzero(c)) == 0
+    a = gpu(inputs.exp_decay(n, 0.1, 3))
+    c, pairs = sp.multiply_precision(a, a, float("inf"), 64, "bf16")
+    assert pairs == 0 and int(torch.count_nonzero(c)) == 0
+
+
+def test_unsupported_shapes_and_arguments():
+    a = gpu(inputs.exp_decay(320, 0.1, 1))
+    with pytest.raises(sp.SpammError) as e:
+        sp.multiply_precision(a, a, 1e-6, 64, "f16x3")  # 320 is not a multiple of 128
+    assert e.value.status == 4
+    b = gpu(inputs.exp_decay(256, 0.1, 1))
+    with pytest.raises(sp.SpammError):
+        sp.multiply_precision(b, b, 1e-6, 32, "bf16")  # leaf 32
+    with pytest.raises(sp.SpammError):
+        sp.multiply_precision(b, b, 1e-6, 64, 7)
+    # FP32 through the same entry point is the plain path
+    c0, p0 = sp.multiply_precision(b, b, 1e-6, 64, "fp32")
+    c1, p1 = sp.multiply(b, b, 1e-6, 64)
+    assert p0 == p1 and torch.equal(c0, c1)
+
+
+def _sample_tiles(bd, seed):
+    rng = np.random.default_rng(seed)
+    ii, jj = np.meshgrid(np.arange(bd), np.arange(bd), indexing="ij")
+    band = np.stack([ii.ravel(), jj.ravel()], 1)
+    band = band[np.abs(band[:, 0] - band[:, 1]) <= 2]
+    pick = rng.choice(len(band), 48, replace=False)
+    rand = rng.integers(0, bd, size=(16, 2))
+    return np.concatenate([band[pick], rand])
+
+
+@pytest.mark.parametrize("kind", ["exp0.05", "relu"])
+def test_precision_forms_full_size_sampled_tiles(kind):
+    # N = 16384, leaf 64, tau = 1e-6: every form on the GPU; the oracle on
+    # sampled output tiles (the band |i - j| <= 2 and random tiles)
+    n, leaf, tau = 16384, 64, 1e-6
+    if kind == "relu":
+        ga, gb = inputs.relu_like_torch(n, 0, DEV), inputs.relu_like_torch(n, 1, DEV)
+    else:
+        ga, gb = inputs.exp_decay_torch(n, 0.05, 0, DEV), inputs.exp_decay_torch(n, 0.05, 1, DEV)
+    a, b = ga.cpu().numpy(), gb.cpu().numpy()
+    bd = n // leaf
+    tiles = _sample_tiles(bd, 3)
+    pa, pb = oracle.pyramid(a, leaf), oracle.pyramid(b, leaf)
+    ea = pr.f16_scale_exponent(float(np.max(pa[-1])))
+    eb = pr.f16_scale_exponent(float(np.max(pb[-1])))
+    ha, la = pr.f16_split(a, ea)
+    hb, lb = pr.f16_split(b, eb)
+    qa = np.ldexp(ha.astype(np.float64) + la, -ea).astype(np.float32)
+    qb = np.ldexp(hb.astype(np.float64) + lb, -eb).astype(np.float32)
+    del ha, hb
+    lla = np.ldexp(la.astype(np.float64), -ea).astype(np.float32)
+    llb = np.ldexp(lb.astype(np.float64), -eb).astype(np.float32)
+    del la, lb
+    ref = {
+        "fp32": oracle.spamm_tiles(a, b, tau, leaf, tiles, pyr_a=pa, pyr_b=pb)[0],
+        "f16x3": oracle.spamm_tiles(qa, qb, tau, leaf, tiles, pyr_a=pa, pyr_b=pb)[0]
+        - oracle.spamm_tiles(lla, llb, tau, leaf, tiles, pyr_a=pa, pyr_b=pb)[0],
+        "bf16": oracle.spamm_tiles(pr.bf16_round(a), pr.bf16_round(b), tau, leaf, tiles, pyr_a=pa, pyr_b=pb)[0],
+    }
+    exact = ref["fp32"]
+    abs_ref = oracle.spamm_tiles(np.abs(a), np.abs(b), tau, leaf, tiles, pyr_a=pa, pyr_b=pb)[0]
+    _, pairs32 = sp.multiply(ga, gb, tau, leaf)
+    for prec, k in (("fp32", n), ("f16x3", 3 * n), ("bf16", n)):
+        c, pairs = sp.multiply_precision(ga, gb, tau, leaf, prec)
+        assert pairs == pairs32
+        got = np.stack([c[i * leaf:(i + 1) * leaf, j * leaf:(j + 1) * leaf].cpu().numpy() for i, j in tiles])
+        err = np.abs(got.astype(np.float64) - ref[prec])
+        assert np.all(err <= gamma(k) * abs_ref * (1 + 2.0**-7) + 1e-300), prec
+        rel = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+        print(f"{kind} {prec}: pairs {pairs}, sampled rel. error vs FP64 SpAMM {rel:.2e}")
+        assert rel <= {"fp32": 1e-5, "f16x3": 1e-6, "bf16": 1e-2}[prec]
