@@ -32,14 +32,17 @@ import numpy as np
 
 ROOT = Path(__file__).resolve().parent
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_F16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 matrix peak
 METRIC = "dense-equiv TFLOP/s & speedup vs dense GEMM at rel. Frobenius err ≤1e-4"
 TRAFFIC_FILE = ROOT / "profiles" / "multiply_traffic.json"
 CSRC = ROOT / "paper_2103_13042_amd" / "csrc"
 CALIB_BYTES = 256 << 20  # device copy whose counter readings scale the HBM byte counters
 
 
-def multiply_kernel(n: int, leaf: int) -> tuple[str, Path]:
-    """Name and source file of the kernel spamm_execute_scheduled launches."""
+def multiply_kernel(n: int, leaf: int, precision: str = "fp32") -> tuple[str, Path]:
+    """Name and source file of the multiply kernel the timed step launches."""
+    if precision != "fp32":
+        return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", CSRC / "multiply_macro.hip"
     if leaf == 64 and n % 128 == 0:
         return "multiply_macro_dma_kernel", CSRC / "multiply_macro.hip"
     if leaf in (32, 64):
@@ -59,6 +62,11 @@ def parse_args():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--tau", type=float, default=1e-6)
+    ap.add_argument("--workload", choices=["alg", "exp", "relu"], default="alg",
+                    help="matrix family (default: algebraic decay)")
+    ap.add_argument("--alpha", type=float, default=0.05, help="decay rate of --workload exp")
+    ap.add_argument("--precision", choices=["fp32", "bf16", "f16x3"], default="fp32",
+                    help="leaf-product precision (the mask is always the FP32 inputs')")
     ap.add_argument("--sweep", default="1e-8,1e-4", help="other tau values timed briefly (empty: none)")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense FP32 GEMM comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
@@ -95,7 +103,8 @@ def _counter_rows(path: str, counter: str):
 def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float, commands: list[str]) -> int:
     """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE)
     into profiles/multiply_traffic.json: per-dispatch KiB of the multiply kernel,
-    each scaled by what the same counter reads for the CALIB_BYTES device copy."""
+    each scaled by what the same counter reads for the CALIB_BYTES device copy.
+    (Default workload and precision only.)"""
     kernel, source = multiply_kernel(n, leaf)
     out = {"kernel": kernel, "workload": workload_name(n, leaf, tau),
            "source": str(source.relative_to(ROOT)),
@@ -121,8 +130,15 @@ def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float,
     return 0
 
 
-def workload_name(n: int, leaf: int, tau: float) -> str:
-    return f"algebraic-decay s_ij/(1+|i-j|)^2, N={n}, leaf {leaf}, tau={tau:g}"
+def workload_name(n: int, leaf: int, tau: float, kind: str = "alg", alpha: float = 0.05,
+                  precision: str = "fp32") -> str:
+    base = {
+        "alg": "algebraic-decay s_ij/(1+|i-j|)^2",
+        "exp": f"exponential-decay exp(-{alpha:g}|i-j|)(0.5+0.5u)",
+        "relu": "ReLU-like (60% zeros, N(0,1) clipped at 0)",
+    }[kind]
+    name = f"{base}, N={n}, leaf {leaf}, tau={tau:g}"
+    return name if precision == "fp32" else f"{name}, {precision} leaf products"
 
 
 def main() -> int:
@@ -149,17 +165,25 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     torch.backends.cuda.matmul.allow_tf32 = False
 
-    n, leaf, tau = args.n, args.leaf, args.tau
+    n, leaf, tau, prec = args.n, args.leaf, args.tau, args.precision
     bd = sp.bdim(n, leaf)
-    log(f"generating inputs N={n}")
+    log(f"generating inputs N={n} ({args.workload})")
     t0 = time.perf_counter()
-    a_np, b_np = inputs.workload_alg8192(n)
-    log(f"inputs ready in {time.perf_counter() - t0:.1f}s; uploading")
-    a = torch.from_numpy(a_np).to(dev)
-    b = torch.from_numpy(b_np).to(dev)
+    if args.workload == "alg":
+        a_np, b_np = inputs.workload_alg8192(n)
+        a = torch.from_numpy(a_np).to(dev)
+        b = torch.from_numpy(b_np).to(dev)
+    else:  # generated on the device; the CPU baseline reads them back
+        if args.workload == "exp":
+            a, b = inputs.exp_decay_torch(n, args.alpha, 0, dev), inputs.exp_decay_torch(n, args.alpha, 1, dev)
+        else:
+            a, b = inputs.relu_like_torch(n, 0, dev), inputs.relu_like_torch(n, 1, dev)
+        a_np = b_np = None
+    log(f"inputs ready in {time.perf_counter() - t0:.1f}s")
     c = torch.empty_like(a)
     ws = sp.workspace(n, leaf, dev)
     bufs = sp.plan_buffers(n, leaf, dev)
+    split_buf = sp.split_buffer(n, prec, dev) if prec != "fp32" else None
 
     # a device-to-device copy of known size, for scaling HBM byte counters
     calib = torch.empty(CALIB_BYTES, dtype=torch.uint8, device=dev)
@@ -171,10 +195,23 @@ def main() -> int:
     # spamm_execute as its two launch steps, so that events on the stream the
     # library launches on (torch's current stream, passed by the binding)
     # bracket the multiply kernel alone.
+    # With reduced-precision products the first stage also writes the split
+    # operands (spamm_prepare_split) and the multiply reads them.
+    def stage_prepare(t):
+        if prec == "fp32":
+            return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
+        return sp.prepare_split(a, b, t, leaf, prec, split_buf, bufs=bufs, ws=ws)
+
+    def stage_multiply(offsets, klist):
+        if prec == "fp32":
+            sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
+        else:
+            sp.execute_split(split_buf, n, leaf, prec, offsets, klist, c=c, ws=ws, scheduled=True)
+
     def step(t):
-        offsets, klist, _ = sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
+        offsets, klist, _ = stage_prepare(t)
         sp.schedule(offsets, klist, n, leaf, ws=ws)
-        sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
+        stage_multiply(offsets, klist)
 
     def timed(t, steps, warmup):
         for _ in range(warmup):
@@ -185,11 +222,11 @@ def main() -> int:
         start.record()
         for e in ev:
             e[0].record()
-            offsets, klist, _ = sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
+            offsets, klist, _ = stage_prepare(t)
             e[1].record()
             sp.schedule(offsets, klist, n, leaf, ws=ws)
             e[2].record()
-            sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
+            stage_multiply(offsets, klist)
             e[3].record()
         end.record()
         torch.cuda.synchronize()
@@ -198,12 +235,14 @@ def main() -> int:
         pairs = int(bufs[2].item())
         return total / steps, stages, pairs
 
-    kname, ksrc = multiply_kernel(n, leaf)
-    workload = workload_name(n, leaf, tau)
+    kname, ksrc = multiply_kernel(n, leaf, prec)
+    workload = workload_name(n, leaf, tau, args.workload, args.alpha, prec)
     log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
     ms_step, (prep_ms, sched_ms, kern_ms), pairs = timed(tau, args.steps, args.warmup)
     dense_equiv = 2.0 * n**3 / (ms_step * 1e-3) / 1e12
-    flops_mul = 2.0 * leaf**3 * pairs
+    # MFMA flops the multiply kernel executes: the three FP16 products triple them
+    flops_mul = 2.0 * leaf**3 * pairs * (3 if prec == "f16x3" else 1)
+    peak = PEAK_FP32_MFMA_TFLOPS if prec == "fp32" else PEAK_F16_MFMA_TFLOPS
     achieved = flops_mul / (kern_ms * 1e-3) / 1e12
     log(f"{ms_step:.3f} ms/step (prepare {prep_ms:.3f}, schedule {sched_ms:.3f}, {kname} {kern_ms:.3f}), "
         f"pairs {pairs}, {dense_equiv:.1f} dense-equiv TFLOP/s, multiply {achieved:.1f} TFLOP/s")
@@ -219,13 +258,14 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16 products, f32 accumulate", "f16x3": "f16 hi+lo products, f32 accumulate"}[prec],
         "data": "synthetic",
         "config": {
             "workload": workload,
             "n": n,
             "leaf": leaf,
             "tau": tau,
+            "precision": prec,
             "pairs": pairs,
             "valid_ratio": pairs / bd**3,
         },
@@ -239,9 +279,9 @@ def main() -> int:
         "flop_per_launch": flops_mul,
         "ms_per_launch": round(kern_ms, 4),
         "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_MFMA_TFLOPS,
+        "peak": peak,
         "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+        "frac": round(achieved / peak, 4),
         "traffic": tr["hbm_bytes_per_launch"] if tr else None,
     }
 
@@ -277,7 +317,7 @@ def main() -> int:
             "ms_per_step": round(ms, 4),
             "dense_equiv_tflops": round(2.0 * n**3 / (ms * 1e-3) / 1e12, 3),
             "multiply_ms": round(em, 4),
-            "mfma_frac": round(2.0 * leaf**3 * p / (em * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+            "mfma_frac": round(flops_mul / pairs * p / (em * 1e-3) / 1e12 / peak, 4) if pairs else None,
             "pairs": p,
         }
         log(f"tau={t:g}: {ms:.3f} ms/step, pairs {p}")
@@ -287,6 +327,10 @@ def main() -> int:
         torch.cuda.synchronize()
 
     if not args.no_cpu_baseline:
+        if a_np is None:
+            a_np, b_np = a.cpu().numpy(), b.cpu().numpy()
+        # the oracle computes the FP32 inputs' SpAMM in FP64: with reduced
+        # precision the sampled difference is that form's error
         result["cpu_baseline"], result["rel_err_vs_oracle_sampled"] = cpu_baseline(
             a_np, b_np, c.cpu().numpy(), tau, leaf, args.cpu_seconds
         )

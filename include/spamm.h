@@ -185,7 +185,15 @@ spamm_status spamm_execute_split_scheduled(const void* split, int64_t n, int32_t
                                            const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
                                            size_t workspace_bytes, void* stream);
 
-/* The whole path with reduced-precision products: spamm_prepare, spamm_split,
+/* spamm_prepare followed by spamm_split on the pyramids it leaves in the
+ * workspace (the first half of spamm_multiply_precision).  Errors as
+ * spamm_prepare and spamm_split. */
+spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                 int32_t precision, int32_t* offsets, int32_t* klist, int64_t klist_capacity,
+                                 int64_t* pairs, void* split, size_t split_bytes, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
+/* The whole path with reduced-precision products: spamm_prepare_split, then
  * spamm_execute_split.  SPAMM_PREC_FP32 is spamm_multiply (split unused, may be
  * NULL).  Errors as spamm_multiply and spamm_split. */
 spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n, double tau, int32_t leaf,

@@ -56,6 +56,7 @@ _SIGS = {
     "spamm_split": (_st, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "spamm_execute_split": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_execute_split_scheduled": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_prepare_split": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_multiply_precision": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_strerror": (ctypes.c_char_p, [_st]),
     "spamm_last_error": (ctypes.c_char_p, []),
@@ -506,9 +507,23 @@ def multiply_precision(a, b, tau: float, leaf: int, precision, *, c=None, pairs=
     c = torch.empty_like(a) if c is None else c
     pairs = torch.empty(1, dtype=torch.int64, device=dev) if pairs is None else pairs
     ws = workspace(n, leaf, dev) if ws is None else ws
-    if split_buf is None and p != 0:
+    if split_buf is None and p in (1, 2):
         split_buf = split_buffer(n, p, dev)
     _check(_lib.spamm_multiply_precision(_ptr(a), _ptr(b), n, float(tau), leaf, p, _ptr(c), _ptr(pairs),
                                          _ptr(split_buf), split_buf.numel() if split_buf is not None else 0,
                                          _ptr(ws), ws.numel(), _stream(dev)), "spamm_multiply_precision")
     return (c, int(pairs.item())) if sync else (c, pairs)
+
+
+def prepare_split(a, b, tau: float, leaf: int, precision, split_buf, *, bufs=None, ws=None):
+    """spamm_prepare + spamm_split on the workspace pyramids: (offsets, klist, pairs)."""
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    dev = a.device
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    offsets, klist, pairs = plan_buffers(n, leaf, dev) if bufs is None else bufs
+    _check(_lib.spamm_prepare_split(_ptr(a), _ptr(b), n, float(tau), leaf, _prec(precision), _ptr(offsets),
+                                    _ptr(klist), klist.numel(), _ptr(pairs), _ptr(split_buf), split_buf.numel(),
+                                    _ptr(ws), ws.numel(), _stream(dev)), "spamm_prepare_split")
+    return offsets, klist, pairs

@@ -446,6 +446,22 @@ spamm_status spamm_execute_split(const void* split, int64_t n, int32_t leaf, int
                                          stream);
 }
 
+spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                 int32_t precision, int32_t* offsets, int32_t* klist, int64_t klist_capacity,
+                                 int64_t* pairs, void* split, size_t split_bytes, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_lowp(g, precision);
+    if (st != SPAMM_OK) return st;
+    st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, klist_capacity, pairs, workspace, workspace_bytes, stream);
+    if (st != SPAMM_OK) return st;
+    const Layout L = make_layout(g);
+    return spamm_split(a, b, n, leaf, precision, at<double>(workspace, L.pyr[0]), at<double>(workspace, L.pyr[1]),
+                       split, split_bytes, stream);
+}
+
 spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
                                       int32_t precision, float* c, int64_t* pairs, void* split, size_t split_bytes,
                                       void* workspace, size_t workspace_bytes, void* stream) {
@@ -463,11 +479,8 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
     int32_t* offsets = at<int32_t>(workspace, L.offsets);
     int32_t* klist = at<int32_t>(workspace, L.klist);
     int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
-    st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
-                       stream);
-    if (st != SPAMM_OK) return st;
-    st = spamm_split(a, b, n, leaf, precision, at<double>(workspace, L.pyr[0]), at<double>(workspace, L.pyr[1]),
-                     split, split_bytes, stream);
+    st = spamm_prepare_split(a, b, n, tau, leaf, precision, offsets, klist, g.ntiles * g.bdim, np, split,
+                             split_bytes, workspace, workspace_bytes, stream);
     if (st != SPAMM_OK) return st;
     return spamm_execute_split(split, n, leaf, precision, offsets, klist, c, workspace, workspace_bytes, stream);
 }
