@@ -163,7 +163,8 @@ spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double ta
 #define SPAMM_PREC_F16X3 2
 
 /* Bytes of the split operands of A and B for a precision (0 for FP32 or bad
- * arguments): a 256-byte header (the two scale exponents), then n*n halves per
+ * arguments): a 256-byte header (int32 scale exponents of A and B at byte 0,
+ * the largest leaf norms as doubles at byte 8), then n*n halves per
  * plane: A (row-major), [A lo], B transposed, [B lo transposed]. */
 size_t spamm_split_bytes(int64_t n, int32_t precision);
 

@@ -18,32 +18,37 @@
 
 namespace spamm {
 
-// e per matrix from the leaf level of its pyramid (one block)
-__global__ __launch_bounds__(1024) void split_scale_kernel(const double* __restrict__ pyr_a,
-                                                           const double* __restrict__ pyr_b, int64_t bdim, int lv,
-                                                           int32_t* __restrict__ exps) {
-    __shared__ double red[16];
+// e per matrix from the leaf level of its pyramid: the largest leaf norm of A
+// and of B (grid-wide maximum of non-negative doubles through their bit
+// patterns, which order like unsigned integers), then e from it.
+__global__ void split_scale_init_kernel(unsigned long long* __restrict__ mx) {
+    if (threadIdx.x < 2) mx[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void split_max_kernel(const double* __restrict__ pyr_a,
+                                                        const double* __restrict__ pyr_b, int64_t bdim, int lv,
+                                                        unsigned long long* __restrict__ mx) {
     const int64_t side = int64_t(1) << lv;
-    for (int m = 0; m < 2; ++m) {
-        const double* leaf = (m == 0 ? pyr_a : pyr_b) + level_offset(lv);
-        double v = 0.0;
-        for (int64_t t = threadIdx.x; t < bdim * bdim; t += 1024) v = fmax(v, leaf[(t / bdim) * side + t % bdim]);
+    const int m = blockIdx.y;
+    const double* leaf = (m == 0 ? pyr_a : pyr_b) + level_offset(lv);
+    double v = 0.0;
+    for (int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x; t < bdim * bdim; t += int64_t(gridDim.x) * 256)
+        v = fmax(v, leaf[(t / bdim) * side + t % bdim]);
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double mx = 0.0;
-            for (int w = 0; w < 16; ++w) mx = fmax(mx, red[w]);
-            int e = 0;
-            if (mx > 0.0) {
-                int x = 0;
-                const double f = frexp(mx, &x);  // mx = f 2^x, f in [0.5, 1)
-                e = 15 - (f == 0.5 ? x - 1 : x);
-            }
-            exps[m] = e;
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(&mx[m], static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+__global__ void split_scale_kernel(const unsigned long long* __restrict__ mx, int32_t* __restrict__ exps) {
+    if (threadIdx.x < 2) {
+        const double m = __longlong_as_double(static_cast<long long>(mx[threadIdx.x]));
+        int e = 0;
+        if (m > 0.0) {
+            int x = 0;
+            const double f = frexp(m, &x);  // m = f 2^x, f in [0.5, 1)
+            e = 15 - (f == 0.5 ? x - 1 : x);
         }
-        __syncthreads();
+        exps[threadIdx.x] = e;
     }
 }
 
@@ -138,7 +143,13 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float* __res
 
 hipError_t launch_split(const float* a, const float* b, int64_t n, int64_t bdim, int lv, const double* pyr_a,
                         const double* pyr_b, int precision, const SplitLayout& L, hipStream_t s) {
-    split_scale_kernel<<<1, 1024, 0, s>>>(pyr_a, pyr_b, bdim, lv, L.exps);
+    // the header holds exps[2] (bytes 0..7) and the two maxima (bytes 8..23)
+    unsigned long long* mx = reinterpret_cast<unsigned long long*>(L.exps + 2);
+    split_scale_init_kernel<<<1, 64, 0, s>>>(mx);
+    const int64_t tiles = bdim * bdim;
+    const unsigned blocks = unsigned(tiles < 64 * 256 ? (tiles + 255) / 256 : 64);
+    split_max_kernel<<<dim3{blocks, 2u, 1u}, 256, 0, s>>>(pyr_a, pyr_b, bdim, lv, mx);
+    split_scale_kernel<<<1, 64, 0, s>>>(mx, L.exps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n4 = n * n / 4;
