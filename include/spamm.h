@@ -201,6 +201,30 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
                                       int32_t precision, float* c, int64_t* pairs, void* split, size_t split_bytes,
                                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* Batches of independent products (each its own n, leaf and tau; the same
+ * result as spamm_multiply on each, up to FP32 accumulation order).  Every
+ * stage of the path is one launch over the whole batch: leaf norms, pyramids,
+ * plan (mask, scan, fill), the per-class cost prefix, and one persistent
+ * multiply launch per leaf class present (32, 64, 128) whose workgroups split
+ * the class's total cost (section 3.5.1's balance, across products).
+ *
+ * spamm_batch_workspace_bytes: device bytes for a batch (0 on bad arguments).
+ * spamm_batch_setup: binds the batch to its matrices.  a, b, c: HOST arrays of
+ *   `count` device pointers (n[p] x n[p] FP32 row-major, c overwritten); n,
+ *   leaf, tau: HOST arrays; pairs: DEVICE int64[count], receives each
+ *   product's kept pairs.  Lays out the workspace and uploads per-product
+ *   descriptors (synchronous).  EINVAL/EUNSUPPORTED per product as
+ *   spamm_multiply (leaf 32, 64 or 128); ENOSPACE: workspace too small.
+ * spamm_batch_run: runs a set-up batch (same count, n, leaf, workspace):
+ *   kernel launches only, no host synchronisation, no allocation and no
+ *   copies, so it can be captured in a graph and replayed. */
+size_t spamm_batch_workspace_bytes(int32_t count, const int64_t* n, const int32_t* leaf);
+spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float* const* b, float* const* c,
+                               const int64_t* n, const int32_t* leaf, const double* tau, int64_t* pairs,
+                               void* workspace, size_t workspace_bytes, void* stream);
+spamm_status spamm_batch_run(int32_t count, const int64_t* n, const int32_t* leaf, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
 /* The valid-ratio search of section 3.5.2: the threshold tau whose valid
  * ratio (kept leaf triples / bdim^3) is within tol of target.  ave is the
  * mean of the norm products over all bdim^3 triples; tau starts at ave; while

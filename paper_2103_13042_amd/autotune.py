@@ -1,0 +1,76 @@
+"""Leaf-size tuner for batches of products.
+
+The leaf edge is part of a SpAMM problem (it decides which tile pairs are
+tested and kept), so the tuner does not change a product behind the caller's
+back: it proposes a leaf per product from measured speed, the caller adopts it
+as part of the problem, and results are checked at the chosen leaf.
+
+``tune`` times the whole single-product path (spamm_multiply) for each
+candidate leaf on one exponential-decay pair per (size, decay-rate) bucket and
+keeps the fastest; ``choose`` maps a product to the nearest bucket in
+(log n, log alpha).
+"""
+
+from __future__ import annotations
+
+import json
+import math
+from pathlib import Path
+
+import numpy as np
+import torch
+
+from . import binding as sp
+from . import inputs
+
+SIZES = (256, 512, 1024, 2048, 4096)
+ALPHAS = (0.01, 0.05, 0.2, 0.5)
+LEAVES = (32, 64, 128)
+
+
+def _time_ms(fn, reps: int) -> float:
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+
+def tune(device, *, tau: float = 1e-6, sizes=SIZES, alphas=ALPHAS, leaves=LEAVES, reps: int = 5) -> dict:
+    """{"buckets": [{"n", "alpha", "ms": {leaf: ms}, "leaf"}], ...}"""
+    rows = []
+    for n in sizes:
+        for al in alphas:
+            a = inputs.exp_decay_torch(n, al, 900, device)
+            b = inputs.exp_decay_torch(n, al, 901, device)
+            c = torch.empty_like(a)
+            ms = {}
+            for leaf in leaves:
+                ws = sp.workspace(n, leaf, device)
+                pairs = torch.empty(1, dtype=torch.int64, device=device)
+                ms[leaf] = _time_ms(lambda: sp.multiply(a, b, tau, leaf, c=c, pairs=pairs, ws=ws, sync=False), reps)
+            rows.append({"n": n, "alpha": al, "ms": {str(k): v for k, v in ms.items()},
+                         "leaf": int(min(ms, key=ms.get))})
+    return {"tau": tau, "leaves": list(leaves), "buckets": rows}
+
+
+def choose(table: dict, n: int, alpha: float) -> int:
+    best, dist = None, math.inf
+    for r in table["buckets"]:
+        d = (math.log(n / r["n"])) ** 2 + (math.log(alpha / r["alpha"])) ** 2
+        if d < dist:
+            best, dist = r["leaf"], d
+    return int(best)
+
+
+def save(table: dict, path) -> None:
+    Path(path).write_text(json.dumps(table, indent=1) + "\n")
+
+
+def load(path) -> dict:
+    return json.loads(Path(path).read_text())

@@ -58,6 +58,9 @@ _SIGS = {
     "spamm_execute_split_scheduled": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare_split": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_multiply_precision": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp]),
+    "spamm_batch_workspace_bytes": (_sz, [_i32, _vp, _vp]),
+    "spamm_batch_setup": (_st, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_batch_run": (_st, [_i32, _vp, _vp, _vp, _sz, _vp]),
     "spamm_strerror": (ctypes.c_char_p, [_st]),
     "spamm_last_error": (ctypes.c_char_p, []),
 }
@@ -527,3 +530,44 @@ def prepare_split(a, b, tau: float, leaf: int, precision, split_buf, *, bufs=Non
                                     _ptr(klist), klist.numel(), _ptr(pairs), _ptr(split_buf), split_buf.numel(),
                                     _ptr(ws), ws.numel(), _stream(dev)), "spamm_prepare_split")
     return offsets, klist, pairs
+
+
+# -- batches of independent products ------------------------------------------
+
+
+class Batch:
+    """A batch bound to its device matrices (spamm_batch_setup); run() enqueues
+    the whole batch (spamm_batch_run) and can be captured in a graph."""
+
+    def __init__(self, a_list, b_list, leaves, taus, *, c_list=None):
+        count = len(a_list)
+        if not (len(b_list) == len(leaves) == len(taus) == count) or count == 0:
+            raise ValueError("a, b, leaves and taus must have the same non-zero length")
+        dev = a_list[0].device
+        ns = []
+        for i, (a, b) in enumerate(zip(a_list, b_list)):
+            n = _square_f32(a, f"a[{i}]")
+            if _square_f32(b, f"b[{i}]") != n or a.device != dev or b.device != dev:
+                raise ValueError(f"product {i}: a and b must be square of the same size on one device")
+            ns.append(n)
+        self.a, self.b = list(a_list), list(b_list)
+        self.c = [torch.empty_like(a) for a in a_list] if c_list is None else list(c_list)
+        self.count, self.device = count, dev
+        self._n = (ctypes.c_int64 * count)(*ns)
+        self._leaf = (ctypes.c_int32 * count)(*[int(v) for v in leaves])
+        self._tau = (ctypes.c_double * count)(*[float(v) for v in taus])
+        nb = int(_lib.spamm_batch_workspace_bytes(count, self._n, self._leaf))
+        if nb == 0:
+            _check(_lib.spamm_batch_setup(count, None, None, None, self._n, self._leaf, self._tau, None, None, 0,
+                                          None), "spamm_batch_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.pairs = torch.zeros(count, dtype=torch.int64, device=dev)
+        ptrs = lambda ts: (ctypes.c_void_p * count)(*[t.data_ptr() for t in ts])
+        _check(_lib.spamm_batch_setup(count, ptrs(self.a), ptrs(self.b), ptrs(self.c), self._n, self._leaf,
+                                      self._tau, _ptr(self.pairs), _ptr(self.ws), self.ws.numel(), _stream(dev)),
+               "spamm_batch_setup")
+
+    def run(self):
+        _check(_lib.spamm_batch_run(self.count, self._n, self._leaf, _ptr(self.ws), self.ws.numel(),
+                                    _stream(self.device)), "spamm_batch_run")
+        return self.c

@@ -137,4 +137,38 @@ hipError_t launch_split(const float* a, const float* b, int64_t n, int64_t bdim,
 hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64_t bdim, int precision,
                                 const uint32_t* items, const int32_t* uprefix, int num_cus, hipStream_t s);
 
+// --------------------------------------------------------------------------
+// Batched products (kernels.hip): one descriptor per product in device memory.
+
+struct BatchProduct {
+    const float* a;
+    const float* b;
+    float* c;
+    double* spyr[2];  // sums of squares (scratch) of A, B
+    double* pyr[2];   // norm pyramids of A, B
+    uint64_t* masks;
+    int32_t* counts;
+    int32_t* bsums;
+    int32_t* boffs;
+    int32_t* offsets;
+    int32_t* klist;
+    int32_t* pair_scratch;
+    int64_t* pairs;  // this product's slot of the caller's pairs array
+    int64_t n, bdim;
+    int32_t leaf, lv, nw, vec;
+    double tau;
+    int64_t tile_base;  // prefix of bdim^2 over the batch
+    int64_t mask_base;  // prefix of nw * bdim over the batch
+    int64_t cost_base;  // written on the device: prefix of multiply cost within its leaf class
+};
+
+// leaf classes of the batched multiply: 32, 64, 128
+constexpr int kBatchClasses = 3;
+
+// members: product indices grouped by class (class_count[c] entries each, in
+// class order); class_total receives each class's total multiply cost.
+hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
+                        const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
+                        int64_t total_mask_blocks, int num_cus, hipStream_t s);
+
 }  // namespace spamm

@@ -143,10 +143,8 @@ hipError_t launch_leaf_norms(const NormJob& job, int nmat, int64_t n, int32_t le
 
 constexpr int kPyrThreads = 1024;
 
-__global__ __launch_bounds__(kPyrThreads) void pyramid_kernel(PyramidJob job, int64_t bdim, int lv) {
-    const int m = blockIdx.x;
-    double* __restrict__ sp = job.spyr[m];
-    double* __restrict__ np = job.pyr[m];
+__device__ __forceinline__ void pyramid_build(double* __restrict__ sp, double* __restrict__ np, int64_t bdim,
+                                              int lv) {
     const int64_t side = int64_t(1) << lv;
     if (bdim < side) {  // padding tiles of the leaf level: norm 0
         const int64_t base = level_offset(lv);
@@ -173,6 +171,10 @@ __global__ __launch_bounds__(kPyrThreads) void pyramid_kernel(PyramidJob job, in
     }
 }
 
+__global__ __launch_bounds__(kPyrThreads) void pyramid_kernel(PyramidJob job, int64_t bdim, int lv) {
+    pyramid_build(job.spyr[blockIdx.x], job.pyr[blockIdx.x], bdim, lv);
+}
+
 hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv, hipStream_t s) {
     pyramid_kernel<<<nmat, kPyrThreads, 0, s>>>(job, bdim, lv);
     return hipGetLastError();
@@ -193,15 +195,14 @@ hipError_t launch_pyramid(const PyramidJob& job, int nmat, int64_t bdim, int lv,
 constexpr int kPlanThreads = 256;
 
 template <bool MASKS, bool SKIPPED>
-__global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* __restrict__ pyr_a,
-                                                                 const double* __restrict__ pyr_b, int64_t bdim,
-                                                                 int lv, double tau, uint64_t* __restrict__ masks,
-                                                                 int32_t* __restrict__ counts,
-                                                                 int32_t* __restrict__ block_sums) {
+__device__ __forceinline__ void plan_mask_block(const double* __restrict__ pyr_a, const double* __restrict__ pyr_b,
+                                                int64_t bdim, int lv, double tau, uint64_t* __restrict__ masks,
+                                                int32_t* __restrict__ counts, int32_t* __restrict__ block_sums,
+                                                int64_t jb, int64_t i) {
     __shared__ double sb[64][65];
     __shared__ int wsum[kPlanThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t i = blockIdx.y, j0 = int64_t(blockIdx.x) * 64;
+    const int64_t j0 = jb * 64;
     const int64_t side = int64_t(1) << lv;
     const int nw = int((bdim + 63) / 64);
     const double* la = pyr_a + level_offset(lv);
@@ -271,7 +272,16 @@ __global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* _
     }
     if (lane == 0) wsum[wave] = tot;
     __syncthreads();
-    if (threadIdx.x == 0) block_sums[i * nw + blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (threadIdx.x == 0) block_sums[i * nw + jb] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+template <bool MASKS, bool SKIPPED>
+__global__ __launch_bounds__(kPlanThreads) void plan_mask_kernel(const double* __restrict__ pyr_a,
+                                                                 const double* __restrict__ pyr_b, int64_t bdim,
+                                                                 int lv, double tau, uint64_t* __restrict__ masks,
+                                                                 int32_t* __restrict__ counts,
+                                                                 int32_t* __restrict__ block_sums) {
+    plan_mask_block<MASKS, SKIPPED>(pyr_a, pyr_b, bdim, lv, tau, masks, counts, block_sums, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_plan_mask(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau, bool skipped,
@@ -332,10 +342,9 @@ hipError_t launch_mean_norm_product(const double* pyr_a, const double* pyr_b, in
 // thread a contiguous segment, wave scans with shuffles, then across waves.
 constexpr int kScanThreads = 256;
 
-__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* __restrict__ block_sums,
-                                                                 int64_t nb, int32_t* block_offsets,
-                                                                 int32_t* offsets, int64_t nt,
-                                                                 int64_t* __restrict__ pairs) {
+__device__ __forceinline__ void plan_scan_block(const int32_t* __restrict__ block_sums, int64_t nb,
+                                                int32_t* block_offsets, int32_t* offsets, int64_t nt,
+                                                int64_t* __restrict__ pairs) {
     __shared__ int64_t wsum[kScanThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t seg = (nb + kScanThreads - 1) / kScanThreads;
@@ -366,6 +375,13 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* 
     }
 }
 
+__global__ __launch_bounds__(kScanThreads) void plan_scan_kernel(const int32_t* __restrict__ block_sums,
+                                                                 int64_t nb, int32_t* block_offsets,
+                                                                 int32_t* offsets, int64_t nt,
+                                                                 int64_t* __restrict__ pairs) {
+    plan_scan_block(block_sums, nb, block_offsets, offsets, nt, pairs);
+}
+
 hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t* block_offsets, int32_t* offsets,
                             int64_t ntiles, int64_t* pairs, hipStream_t s) {
     plan_scan_kernel<<<1, kScanThreads, 0, s>>>(block_sums, nblocks, block_offsets, offsets, ntiles, pairs);
@@ -376,14 +392,11 @@ hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t*
 // of 64 tiles plus the counts of the tiles before it in the block (a masked
 // wave sum); then every lane whose bit is set writes its k at the offset plus
 // the number of set bits below it (ascending k).
-__global__ __launch_bounds__(256) void plan_fill_kernel(const uint64_t* __restrict__ masks,
-                                                        const int32_t* __restrict__ counts,
-                                                        const int32_t* __restrict__ block_offsets, int64_t bdim,
-                                                        int32_t* __restrict__ offsets, int32_t* __restrict__ klist) {
+__device__ __forceinline__ void plan_fill_wave(const uint64_t* __restrict__ masks, const int32_t* __restrict__ counts,
+                                               const int32_t* __restrict__ block_offsets, int64_t bdim,
+                                               int32_t* __restrict__ offsets, int32_t* __restrict__ klist,
+                                               int64_t t) {
     const int lane = threadIdx.x & 63;
-    const int64_t nt = bdim * bdim;
-    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (t >= nt) return;
     const int nw = int((bdim + 63) / 64);
     const int64_t i = t / bdim, j = t % bdim, jb = j >> 6;
     const int64_t jl = (jb * 64 + lane < bdim) ? jb * 64 + lane : -1;  // the block's tile for this lane
@@ -398,6 +411,15 @@ __global__ __launch_bounds__(256) void plan_fill_kernel(const uint64_t* __restri
         if ((m >> lane) & 1ull) klist[base + __popcll(m & below)] = w * 64 + lane;
         base += __popcll(m);
     }
+}
+
+__global__ __launch_bounds__(256) void plan_fill_kernel(const uint64_t* __restrict__ masks,
+                                                        const int32_t* __restrict__ counts,
+                                                        const int32_t* __restrict__ block_offsets, int64_t bdim,
+                                                        int32_t* __restrict__ offsets, int32_t* __restrict__ klist) {
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= bdim * bdim) return;
+    plan_fill_wave(masks, counts, block_offsets, bdim, offsets, klist, t);
 }
 
 hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* counts, const int32_t* block_offsets,
@@ -527,30 +549,19 @@ __device__ __forceinline__ int64_t partition_start(const int32_t* __restrict__ o
     return lo;
 }
 
+// The multiply of the output tiles [t_begin, t_end) of one product, by one
+// workgroup: lds holds the two staging buffers, ring the pair ring.
 template <int LEAF, bool VEC>
-__global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_kernel(const float* __restrict__ A,
-                                                                  const float* __restrict__ B, float* __restrict__ C,
-                                                                  int64_t n, int64_t bdim,
-                                                                  const int32_t* __restrict__ off,
-                                                                  const int32_t* __restrict__ klist,
-                                                                  int32_t* pairs) {
+__device__ __forceinline__ void mul_range(const float* __restrict__ A, const float* __restrict__ B,
+                                          float* __restrict__ C, int64_t n, int64_t bdim,
+                                          const int32_t* __restrict__ off, const int32_t* __restrict__ klist,
+                                          int32_t* pairs, int64_t t_begin, int64_t t_end, float* lds,
+                                          int32_t* ring) {
     using Gm = MulGeom<LEAF>;
     using M = Mfma<Gm::MF>;
-    __shared__ __attribute__((aligned(16))) float lds[2 * Gm::STAGE];
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int ir = lane % Gm::MF, g = lane / Gm::MF;
-
-    // this group's range of output tiles
-    const int64_t groups = gridDim.x;
-    const int64_t bid = blockIdx.x;
-    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
-    const int64_t nt = bdim * bdim;
-    const int64_t total = int64_t(kPairCost) * off[nt] + nt;
-    const int64_t t_begin = partition_start(off, nt, lg, groups, total);
-    const int64_t t_end = partition_start(off, nt, lg + 1, groups, total);
-    if (t_begin >= t_end) return;
     const int64_t q_begin = off[t_begin], q_end = off[t_end];
     const int64_t nitems = (q_end - q_begin) * Gm::NCH;
 
@@ -568,7 +579,6 @@ __global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_kerne
         pairs[q] = (ti << (2 * kIdxBits)) | (tj << kIdxBits) | klist[q];
     }
     __syncthreads();
-    __shared__ int32_t ring[kRing];
     const int64_t npairs = q_end - q_begin;
     for (int e = tid; e < kRing; e += kMulThreads) ring[e] = e < npairs ? pairs[q_begin + e] : 0;
     __syncthreads();
@@ -736,6 +746,28 @@ __global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_kerne
     while (t < t_end) advance_tile();
 }
 
+
+template <int LEAF, bool VEC>
+__global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_kernel(const float* __restrict__ A,
+                                                                  const float* __restrict__ B, float* __restrict__ C,
+                                                                  int64_t n, int64_t bdim,
+                                                                  const int32_t* __restrict__ off,
+                                                                  const int32_t* __restrict__ klist,
+                                                                  int32_t* pairs) {
+    __shared__ __attribute__((aligned(16))) float lds[2 * MulGeom<LEAF>::STAGE];
+    __shared__ int32_t ring[kRing];
+    // this group's range of output tiles
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t nt = bdim * bdim;
+    const int64_t total = int64_t(kPairCost) * off[nt] + nt;
+    const int64_t t_begin = partition_start(off, nt, lg, groups, total);
+    const int64_t t_end = partition_start(off, nt, lg + 1, groups, total);
+    if (t_begin >= t_end) return;
+    mul_range<LEAF, VEC>(A, B, C, n, bdim, off, klist, pairs, t_begin, t_end, lds, ring);
+}
+
 template <int LEAF>
 static hipError_t launch_mul(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
                              const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
@@ -763,6 +795,201 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
         case 128: return launch_mul<128>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// --------------------------------------------------------------------------
+// Batched products.  Every stage of the path runs as one launch over all
+// products (the multiply as one persistent launch per leaf class present): a
+// block finds its product by binary search over the prefix of its work in the
+// descriptor array, then runs the single-product code on it.
+
+__device__ __forceinline__ int32_t batch_find(const BatchProduct* __restrict__ P, int32_t count, int64_t x,
+                                              bool by_mask) {
+    int32_t lo = 0, hi = count - 1;  // last p with base(p) <= x
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        const int64_t base = by_mask ? P[mid].mask_base : P[mid].tile_base;
+        if (base <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// leaf norms: one block per leaf tile of A (blockIdx.y = 0) or B (1)
+__global__ __launch_bounds__(kNormThreads) void batch_norms_kernel(const BatchProduct* __restrict__ P, int32_t count,
+                                                                   int64_t total_tiles) {
+    __shared__ double partial[kNormThreads / 64];
+    const int m = blockIdx.y;
+    for (int64_t tg = blockIdx.x; tg < total_tiles; tg += gridDim.x) {
+        const BatchProduct& q = P[batch_find(P, count, tg, false)];
+        const int64_t t = tg - q.tile_base, ti = t / q.bdim, tj = t - (t / q.bdim) * q.bdim;
+        const int64_t n = q.n, leaf = q.leaf;
+        const float* __restrict__ x = m == 0 ? q.a : q.b;
+        const int64_t rows = (ti * leaf + leaf < n ? leaf : n - ti * leaf);
+        const int64_t cols = (tj * leaf + leaf < n ? leaf : n - tj * leaf);
+        double acc = 0.0;
+        if (q.vec && cols == leaf) {  // whole rows of float4
+            const int64_t c4n = leaf / 4;
+            for (int64_t e = threadIdx.x; e < rows * c4n; e += kNormThreads) {
+                const int64_t r = ti * leaf + e / c4n, c = tj * leaf + 4 * (e % c4n);
+                const f4 v = *reinterpret_cast<const f4*>(x + r * n + c);
+                acc += double(v.x) * double(v.x) + double(v.y) * double(v.y) + double(v.z) * double(v.z) +
+                       double(v.w) * double(v.w);
+            }
+        } else {
+            for (int64_t e = threadIdx.x; e < rows * cols; e += kNormThreads) {
+                const int64_t r = ti * leaf + e / cols, c = tj * leaf + e % cols;
+                const double v = double(x[r * n + c]);
+                acc += v * v;
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((threadIdx.x & 63) == 0) partial[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < kNormThreads / 64; ++w) sum += partial[w];
+            const int64_t at = level_offset(q.lv) + ti * (int64_t(1) << q.lv) + tj;
+            q.spyr[m][at] = sum;
+            q.pyr[m][at] = sqrt(sum);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kPyrThreads) void batch_pyramid_kernel(const BatchProduct* __restrict__ P) {
+    const BatchProduct& q = P[blockIdx.x];
+    pyramid_build(q.spyr[blockIdx.y], q.pyr[blockIdx.y], q.bdim, q.lv);
+}
+
+__global__ __launch_bounds__(kPlanThreads) void batch_plan_mask_kernel(const BatchProduct* __restrict__ P,
+                                                                       int32_t count, int64_t total_blocks) {
+    for (int64_t bg = blockIdx.x; bg < total_blocks; bg += gridDim.x) {
+        const BatchProduct& q = P[batch_find(P, count, bg, true)];
+        const int64_t b = bg - q.mask_base;
+        plan_mask_block<true, false>(q.pyr[0], q.pyr[1], q.bdim, q.lv, q.tau, q.masks, q.counts, q.bsums, b % q.nw,
+                                     b / q.nw);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void batch_plan_scan_kernel(const BatchProduct* __restrict__ P) {
+    const BatchProduct& q = P[blockIdx.x];
+    plan_scan_block(q.bsums, q.bdim * q.nw, q.boffs, q.offsets, q.bdim * q.bdim, q.pairs);
+}
+
+__global__ __launch_bounds__(256) void batch_plan_fill_kernel(const BatchProduct* __restrict__ P, int32_t count,
+                                                              int64_t total_tiles) {
+    for (int64_t tg = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); tg < total_tiles; tg += int64_t(gridDim.x) * 4) {
+        const BatchProduct& q = P[batch_find(P, count, tg, false)];
+        plan_fill_wave(q.masks, q.counts, q.boffs, q.bdim, q.offsets, q.klist, tg - q.tile_base);
+    }
+}
+
+// per class, the prefix of multiply cost (kPairCost per kept pair + 1 per
+// tile, as in the single-product partition) over its members, in order
+__global__ void batch_cost_kernel(BatchProduct* __restrict__ P, const int32_t* __restrict__ members, int32_t c0,
+                                  int32_t c1, int32_t c2, int64_t* __restrict__ class_total) {
+    const int c = threadIdx.x;
+    if (c >= kBatchClasses) return;
+    const int32_t cnt[kBatchClasses] = {c0, c1, c2};
+    int32_t first = 0;
+    for (int k = 0; k < c; ++k) first += cnt[k];
+    int64_t run = 0;
+    for (int32_t k = 0; k < cnt[c]; ++k) {
+        BatchProduct& q = P[members[first + k]];
+        q.cost_base = run;
+        run += int64_t(kPairCost) * (*q.pairs) + q.bdim * q.bdim;
+    }
+    class_total[c] = run;
+}
+
+// first tile t of product q whose cost position reaches target / groups
+__device__ __forceinline__ int64_t batch_partition(const BatchProduct& q, int64_t g, int64_t groups, int64_t total) {
+    const int64_t target = g * total, nt = q.bdim * q.bdim;
+    int64_t lo = 0, hi = nt;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((q.cost_base + int64_t(kPairCost) * q.offsets[mid] + mid) * groups >= target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int LEAF>
+__global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_batch_kernel(
+    const BatchProduct* __restrict__ P, const int32_t* __restrict__ members, int32_t nmem,
+    const int64_t* __restrict__ class_total, int cls) {
+    __shared__ __attribute__((aligned(16))) float lds[2 * MulGeom<LEAF>::STAGE];
+    __shared__ int32_t ring[kRing];
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t total = class_total[cls];
+    // members whose cost range meets [lg, lg + 1) * total / groups
+    int32_t lo = 0, hi = nmem - 1;  // last member with cost_base * groups <= lg * total
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (P[members[mid]].cost_base * groups <= lg * total)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    for (int32_t k = lo; k < nmem; ++k) {
+        const BatchProduct& q = P[members[k]];
+        if (q.cost_base * groups >= (lg + 1) * total) break;
+        const int64_t t0 = batch_partition(q, lg, groups, total), t1 = batch_partition(q, lg + 1, groups, total);
+        if (t0 >= t1) continue;
+        if (q.vec)
+            mul_range<LEAF, true>(q.a, q.b, q.c, q.n, q.bdim, q.offsets, q.klist, q.pair_scratch, t0, t1, lds, ring);
+        else
+            mul_range<LEAF, false>(q.a, q.b, q.c, q.n, q.bdim, q.offsets, q.klist, q.pair_scratch, t0, t1, lds,
+                                   ring);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
+                        const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
+                        int64_t total_mask_blocks, int num_cus, hipStream_t s) {
+    auto blocks = [](int64_t work, int64_t cap) { return unsigned(work < cap ? (work > 0 ? work : 1) : cap); };
+    batch_norms_kernel<<<dim3{blocks(total_tiles, 1 << 20), 2u, 1u}, kNormThreads, 0, s>>>(prods, count, total_tiles);
+    batch_pyramid_kernel<<<dim3{unsigned(count), 2u, 1u}, kPyrThreads, 0, s>>>(prods);
+    batch_plan_mask_kernel<<<blocks(total_mask_blocks, 1 << 20), kPlanThreads, 0, s>>>(prods, count,
+                                                                                       total_mask_blocks);
+    batch_plan_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
+    batch_plan_fill_kernel<<<blocks((total_tiles + 3) / 4, 1 << 20), 256, 0, s>>>(prods, count, total_tiles);
+    batch_cost_kernel<<<1, 64, 0, s>>>(const_cast<BatchProduct*>(prods), members, class_count_host[0],
+                                       class_count_host[1], class_count_host[2], class_total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int32_t first = 0;
+    for (int c = 0; c < kBatchClasses; ++c) {
+        const int32_t nmem = class_count_host[c];
+        if (nmem > 0) {
+            const unsigned groups = unsigned(num_cus * 2);
+            switch (c) {
+                case 0:
+                    multiply_batch_kernel<32><<<groups, kMulThreads, 0, s>>>(prods, members + first, nmem,
+                                                                             class_total, c);
+                    break;
+                case 1:
+                    multiply_batch_kernel<64><<<groups, kMulThreads, 0, s>>>(prods, members + first, nmem,
+                                                                             class_total, c);
+                    break;
+                default:
+                    multiply_batch_kernel<128><<<groups, kMulThreads, 0, s>>>(prods, members + first, nmem,
+                                                                              class_total, c);
+                    break;
+            }
+        }
+        first += nmem;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace spamm

@@ -226,3 +226,17 @@ def relu_like_torch(n: int, seed: int, device):
         return torch.where(keep, z.clamp_min(0.0), torch.zeros_like(z))
 
     return _build_torch(n, device, fn)
+
+
+def batch_specs(count: int = 256, seed: int = 13, n_lo: int = 256, n_hi: int = 4096):
+    """(n, alpha_A, alpha_B, seed_A, seed_B) of `count` independent products:
+    n log-uniform in [n_lo, n_hi], decay rates uniform in [0.01, 0.5)."""
+    out = []
+    for q in range(count):
+        i = np.array([q], dtype=np.int64)
+        u = float(uniform01(seed, i, np.array([0]))[0])
+        n = int(round(n_lo * (n_hi / n_lo) ** u))
+        aa = 0.01 + 0.49 * float(uniform01(seed, i, np.array([1]))[0])
+        ab = 0.01 + 0.49 * float(uniform01(seed, i, np.array([2]))[0])
+        out.append((n, aa, ab, 5000 + 2 * q, 5001 + 2 * q))
+    return out

@@ -1,0 +1,109 @@
+"""Batched products on the GPU (spamm_batch_setup / spamm_batch_run): every
+product equals the oracle (pairs exactly; C within the FP32 accumulation bound
+of the single-product tests) or, at sizes the oracle is slow for, the
+single-product path (same pairs; relative Frobenius difference <= 1e-6, the two
+only differ in accumulation order); replays of a captured graph equal the eager
+run bitwise."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_13042_amd import binding as sp
+from paper_2103_13042_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+U32 = 2.0**-24
+
+# (n, leaf, tau, generator) — ragged sizes, n < leaf, a single element, all leaf classes
+SPECS = [
+    (300, 32, 1e-6, "exp"), (1024, 64, 1e-6, "exp"), (777, 128, 1e-6, "exp"), (256, 32, 1e-3, "alg"),
+    (100, 128, 1e-6, "exp"), (1, 32, 0.0, "exp"), (512, 64, 0.0, "alg"), (640, 32, 1e-6, "alg"),
+    (2048, 64, 1e-6, "alg"), (1536, 128, 1e-5, "exp"),
+]
+
+
+def _mats(n, kind, seed):
+    if kind == "exp":
+        return inputs.exp_decay(n, 0.05, seed), inputs.exp_decay(n, 0.08, seed + 1)
+    return inputs.algebraic_decay_signed(n, seed), inputs.algebraic_decay_signed(n, seed + 1)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    mats = [_mats(n, kind, 10 * q) for q, (n, _, _, kind) in enumerate(SPECS)]
+    ga = [torch.from_numpy(a).to(DEV) for a, _ in mats]
+    gb = [torch.from_numpy(b).to(DEV) for _, b in mats]
+    bt = sp.Batch(ga, gb, [s[1] for s in SPECS], [s[2] for s in SPECS])
+    bt.run()
+    torch.cuda.synchronize()
+    return mats, bt
+
+
+def test_batch_matches_oracle_and_single_products(batch):
+    mats, bt = batch
+    pairs = bt.pairs.cpu().tolist()
+    for q, ((n, leaf, tau, _), (a, b)) in enumerate(zip(SPECS, mats)):
+        c = bt.c[q].cpu().numpy()
+        if n <= 1024:
+            c_ref, count, _ = oracle.spamm(a, b, tau, leaf)
+            abs_ref, _, _ = oracle.spamm(np.abs(a), np.abs(b), tau, leaf)
+            assert pairs[q] == count, q
+            bound = n * U32 / (1 - n * U32) * abs_ref + 1e-38
+            assert np.all(np.abs(c.astype(np.float64) - c_ref) <= bound), q
+        c1, p1 = sp.multiply(torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV), tau, leaf)
+        assert pairs[q] == p1, q
+        c1 = c1.cpu().numpy().astype(np.float64)
+        den = np.linalg.norm(c1)
+        assert np.linalg.norm(c - c1) <= 1e-6 * den + 1e-30, q
+
+
+def test_batch_reruns_are_bitwise_equal(batch):
+    _, bt = batch
+    first = [c.clone() for c in bt.c]
+    for c in bt.c:
+        c.fill_(7.0)
+    bt.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(first, bt.c))
+
+
+def test_graph_replays_equal_eager_run(batch):
+    _, bt = batch
+    eager = [c.clone() for c in bt.c]
+    eager_pairs = bt.pairs.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    for r in range(3):
+        for c in bt.c:
+            c.zero_()  # eager work between replays
+        bt.pairs.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(torch.equal(x, y) for x, y in zip(eager, bt.c)), r
+        assert torch.equal(eager_pairs, bt.pairs), r
+
+
+def test_batch_argument_errors():
+    a = torch.ones(64, 64, device=DEV)
+    with pytest.raises(sp.SpammError):
+        sp.Batch([a], [a], [16], [1e-6])  # leaf 16 has no multiply kernel
+    with pytest.raises(sp.SpammError):
+        sp.Batch([a], [a], [32], [-1.0])
+    with pytest.raises(ValueError):
+        sp.Batch([a], [torch.ones(32, 32, device=DEV)], [32], [1e-6])
+    with pytest.raises(sp.SpammError):
+        sp.Batch([a, a], [a, a], [32, 64], [1e-6, 1e-6], c_list=[a, torch.ones(64, 64, device=DEV)])  # c aliases a
