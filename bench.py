@@ -66,6 +66,7 @@ def parse_args():
                     help="matrix family (default: algebraic decay); batch: 256 independent products")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-leaf", type=int, default=0, help="one leaf for every product (0: autotuned)")
+    ap.add_argument("--retune", default="", help="re-run the leaf tuner and write its table to this path")
     ap.add_argument("--alpha", type=float, default=0.05, help="decay rate of --workload exp")
     ap.add_argument("--precision", choices=["fp32", "bf16", "f16x3"], default="fp32",
                     help="leaf-product precision (the mask is always the FP32 inputs')")
@@ -359,9 +360,15 @@ def run_batch(args, torch, sp, inputs, dev) -> int:
     if args.batch_leaf:
         leaves, table = [args.batch_leaf] * len(specs), None
     else:
-        log("autotuning leaf sizes")
         t0 = time.perf_counter()
-        table = autotune.tune(dev, tau=tau)
+        if autotune.TABLE_FILE.exists() and not args.retune:
+            log(f"leaf sizes from {autotune.TABLE_FILE.name}")
+            table = autotune.load(autotune.TABLE_FILE)
+        else:
+            log("autotuning leaf sizes")
+            table = autotune.tune(dev, tau=tau)
+            if args.retune:
+                autotune.save(table, args.retune)
         tune_s = time.perf_counter() - t0
         leaves = [autotune.choose(table, n, math.sqrt(aa * ab)) for n, aa, ab, _, _ in specs]
     bt = sp.Batch(a_l, b_l, leaves, [tau] * len(specs))

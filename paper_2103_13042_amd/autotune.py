@@ -6,9 +6,12 @@ back: it proposes a leaf per product from measured speed, the caller adopts it
 as part of the problem, and results are checked at the chosen leaf.
 
 ``tune`` times the whole single-product path (spamm_multiply) for each
-candidate leaf on one exponential-decay pair per (size, decay-rate) bucket and
-keeps the fastest; ``choose`` maps a product to the nearest bucket in
-(log n, log alpha).
+candidate leaf on one exponential-decay pair per (size, decay-rate) bucket; a
+bucket keeps the default leaf unless another is faster by more than
+``MARGIN`` (so timing noise does not flip the choice).  ``choose`` maps a
+product to the nearest bucket in (log n, log alpha).  The table of the last
+tuning run is kept in ``data/leaf_table.json`` so that the same batch gets the
+same leaves from run to run.
 """
 
 from __future__ import annotations
@@ -26,6 +29,9 @@ from . import inputs
 SIZES = (256, 512, 1024, 2048, 4096)
 ALPHAS = (0.01, 0.05, 0.2, 0.5)
 LEAVES = (32, 64, 128)
+DEFAULT_LEAF = 64
+MARGIN = 0.10
+TABLE_FILE = Path(__file__).resolve().parent / "data" / "leaf_table.json"
 
 
 def _time_ms(fn, reps: int) -> float:
@@ -41,7 +47,7 @@ def _time_ms(fn, reps: int) -> float:
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
 
 
-def tune(device, *, tau: float = 1e-6, sizes=SIZES, alphas=ALPHAS, leaves=LEAVES, reps: int = 5) -> dict:
+def tune(device, *, tau: float = 1e-6, sizes=SIZES, alphas=ALPHAS, leaves=LEAVES, reps: int = 9) -> dict:
     """{"buckets": [{"n", "alpha", "ms": {leaf: ms}, "leaf"}], ...}"""
     rows = []
     for n in sizes:
@@ -54,9 +60,11 @@ def tune(device, *, tau: float = 1e-6, sizes=SIZES, alphas=ALPHAS, leaves=LEAVES
                 ws = sp.workspace(n, leaf, device)
                 pairs = torch.empty(1, dtype=torch.int64, device=device)
                 ms[leaf] = _time_ms(lambda: sp.multiply(a, b, tau, leaf, c=c, pairs=pairs, ws=ws, sync=False), reps)
-            rows.append({"n": n, "alpha": al, "ms": {str(k): v for k, v in ms.items()},
-                         "leaf": int(min(ms, key=ms.get))})
-    return {"tau": tau, "leaves": list(leaves), "buckets": rows}
+            best = min(ms, key=ms.get)
+            if DEFAULT_LEAF in ms and ms[best] > (1.0 - MARGIN) * ms[DEFAULT_LEAF]:
+                best = DEFAULT_LEAF
+            rows.append({"n": n, "alpha": al, "ms": {str(k): v for k, v in ms.items()}, "leaf": int(best)})
+    return {"tau": tau, "leaves": list(leaves), "margin": MARGIN, "default": DEFAULT_LEAF, "buckets": rows}
 
 
 def choose(table: dict, n: int, alpha: float) -> int:

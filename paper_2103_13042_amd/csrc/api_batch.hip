@@ -15,6 +15,7 @@ using namespace spamm_host;
 namespace {
 
 constexpr size_t kAlignB = 256;
+constexpr int64_t kNormCols = 1024;  // columns per block of the norm pass
 size_t up(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
 
 int leaf_class(int32_t leaf) { return leaf == 32 ? 0 : leaf == 64 ? 1 : leaf == 128 ? 2 : -1; }
@@ -23,7 +24,7 @@ struct BatchPlan {
     size_t header = 0, total = 0;
     std::vector<size_t> base;  // per product region offset
     std::vector<Geom> geom;
-    int64_t tiles = 0, mask_blocks = 0;
+    int64_t tiles = 0, mask_blocks = 0, strips = 0;
     int32_t class_count[spamm::kBatchClasses] = {0, 0, 0};
 };
 
@@ -53,6 +54,7 @@ spamm_status plan_batch(int32_t count, const int64_t* n, const int32_t* leaf, Ba
         o += product_bytes(g);
         bp->tiles += g.ntiles;
         bp->mask_blocks += g.bdim * g.nwords;
+        bp->strips += g.bdim * ((g.n + kNormCols - 1) / kNormCols);
         ++bp->class_count[leaf_class(leaf[p])];
     }
     bp->total = o;
@@ -84,7 +86,7 @@ spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float
     std::vector<int32_t> members;
     members.reserve(size_t(count));
     char* ws = static_cast<char*>(workspace);
-    int64_t tile_base = 0, mask_base = 0;
+    int64_t tile_base = 0, mask_base = 0, norm_base = 0;
     for (int32_t p = 0; p < count; ++p) {
         const Geom& g = bp.geom[size_t(p)];
         if ((st = check_mul_args(g, a[p], b[p], c[p])) != SPAMM_OK || (st = check_tau(tau[p])) != SPAMM_OK) {
@@ -123,8 +125,10 @@ spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float
         q.tau = tau[p];
         q.tile_base = tile_base;
         q.mask_base = mask_base;
+        q.norm_base = norm_base;
         tile_base += g.ntiles;
         mask_base += g.bdim * g.nwords;
+        norm_base += g.bdim * ((g.n + kNormCols - 1) / kNormCols);
     }
     for (int cls = 0; cls < spamm::kBatchClasses; ++cls)
         for (int32_t p = 0; p < count; ++p)
@@ -158,7 +162,7 @@ spamm_status spamm_batch_run(int32_t count, const int64_t* n, const int32_t* lea
     int cus = device_cus();
     cus = (cus + 3) / 4 * 4;  // two groups per CU, a multiple of 8 in all
     return hip_check(spamm::launch_batch(prods, count, members, bp.class_count, class_total, bp.tiles,
-                                         bp.mask_blocks, cus, static_cast<hipStream_t>(stream)),
+                                         bp.mask_blocks, bp.strips, cus, static_cast<hipStream_t>(stream)),
                      "batch kernels");
 }
 

@@ -159,6 +159,7 @@ struct BatchProduct {
     double tau;
     int64_t tile_base;  // prefix of bdim^2 over the batch
     int64_t mask_base;  // prefix of nw * bdim over the batch
+    int64_t norm_base;  // prefix of bdim * ceil(n / 1024) (norm-pass strips) over the batch
     int64_t cost_base;  // written on the device: prefix of multiply cost within its leaf class
 };
 
@@ -169,6 +170,6 @@ constexpr int kBatchClasses = 3;
 // class order); class_total receives each class's total multiply cost.
 hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
                         const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
-                        int64_t total_mask_blocks, int num_cus, hipStream_t s);
+                        int64_t total_mask_blocks, int64_t total_strips, int num_cus, hipStream_t s);
 
 }  // namespace spamm

@@ -25,13 +25,14 @@ namespace spamm {
 constexpr int kNormThreads = 256;
 constexpr int kNormCols = kNormThreads * 4;
 
+// strip `strip` (tile row) x column chunk `chunk` of x; tile (strip, tj) goes to
+// sumsq / norms[strip * ld + tj] (either may be null)
 template <int LEAF, bool VEC>
-__global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, int64_t n, int64_t bdim) {
+__device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, int64_t n, int64_t bdim, int64_t strip,
+                                                 int64_t chunk, double* sumsq, double* norms, int64_t ld) {
     constexpr int G = LEAF / 4;  // threads per tile
-    const int m = blockIdx.z;
-    const float* __restrict__ x = job.x[m];
-    const int64_t col = int64_t(blockIdx.x) * kNormCols + 4 * threadIdx.x;
-    const int64_t r0 = int64_t(blockIdx.y) * LEAF;
+    const int64_t col = chunk * kNormCols + 4 * threadIdx.x;
+    const int64_t r0 = strip * LEAF;
     const int64_t r1 = r0 + LEAF < n ? r0 + LEAF : n;
     double acc0 = 0.0, acc1 = 0.0;
     if (VEC) {
@@ -54,19 +55,22 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, i
                 acc1 += double(v.z) * double(v.z) + double(v.w) * double(v.w);
             }
         }
-    } else {
-        for (int e = 0; e < 4; ++e) {
-            const int64_t c = col + e;
-            if (c >= n) break;
-            double acc = 0.0;
-            for (int64_t r = r0; r < r1; ++r) {
-                const double v = double(x[r * n + c]);
-                acc += v * v;
+    } else {  // rows not 16-byte aligned: four 4-byte loads per row, row by row
+        if (col < n) {
+            const int lim = int(n - col < 4 ? n - col : 4);
+            const float* p = x + r0 * n + col;
+            for (int64_t r = r0; r < r1; ++r, p += n) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (e < lim) {
+                        const double v = double(p[e]);
+                        if (e & 1)
+                            acc1 += v * v;
+                        else
+                            acc0 += v * v;
+                    }
+                }
             }
-            if (e & 1)
-                acc1 += acc;
-            else
-                acc0 += acc;
         }
     }
     double s = acc0 + acc1;
@@ -74,10 +78,16 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, i
     for (int off = 1; off < G; off <<= 1) s += __shfl_xor(s, off);
     const int64_t tj = col / LEAF;
     if ((threadIdx.x % G) == 0 && tj < bdim) {
-        const int64_t t = int64_t(blockIdx.y) * job.ld + tj;
-        if (job.sumsq[m]) job.sumsq[m][t] = s;
-        if (job.norms[m]) job.norms[m][t] = sqrt(s);
+        const int64_t t = strip * ld + tj;
+        if (sumsq) sumsq[t] = s;
+        if (norms) norms[t] = sqrt(s);
     }
+}
+
+template <int LEAF, bool VEC>
+__global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, int64_t n, int64_t bdim) {
+    const int m = blockIdx.z;
+    leaf_sumsq_strip<LEAF, VEC>(job.x[m], n, bdim, blockIdx.y, blockIdx.x, job.sumsq[m], job.norms[m], job.ld);
 }
 
 // Any other leaf size: one block per tile, strided over its elements.
@@ -803,12 +813,16 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
 // block finds its product by binary search over the prefix of its work in the
 // descriptor array, then runs the single-product code on it.
 
+constexpr int kFindTile = 0, kFindMask = 1, kFindNorm = 2;
+
 __device__ __forceinline__ int32_t batch_find(const BatchProduct* __restrict__ P, int32_t count, int64_t x,
-                                              bool by_mask) {
+                                              int which) {
     int32_t lo = 0, hi = count - 1;  // last p with base(p) <= x
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
-        const int64_t base = by_mask ? P[mid].mask_base : P[mid].tile_base;
+        const int64_t base = which == kFindMask ? P[mid].mask_base
+                             : which == kFindNorm ? P[mid].norm_base
+                                                  : P[mid].tile_base;
         if (base <= x)
             lo = mid;
         else
@@ -817,45 +831,30 @@ __device__ __forceinline__ int32_t batch_find(const BatchProduct* __restrict__ P
     return lo;
 }
 
-// leaf norms: one block per leaf tile of A (blockIdx.y = 0) or B (1)
+// leaf norms: one block per (tile row, 1024-column chunk) of A (blockIdx.y = 0)
+// or B (1), as in the single-product pass
+template <int LEAF>
+__device__ __forceinline__ void batch_strip(const BatchProduct& q, int m, int64_t b) {
+    const int64_t chunks = (q.n + kNormCols - 1) / kNormCols;
+    const int64_t side = int64_t(1) << q.lv, at = level_offset(q.lv);
+    const float* x = m == 0 ? q.a : q.b;
+    if (q.vec)
+        leaf_sumsq_strip<LEAF, true>(x, q.n, q.bdim, b / chunks, b % chunks, q.spyr[m] + at, q.pyr[m] + at, side);
+    else
+        leaf_sumsq_strip<LEAF, false>(x, q.n, q.bdim, b / chunks, b % chunks, q.spyr[m] + at, q.pyr[m] + at, side);
+}
+
 __global__ __launch_bounds__(kNormThreads) void batch_norms_kernel(const BatchProduct* __restrict__ P, int32_t count,
-                                                                   int64_t total_tiles) {
-    __shared__ double partial[kNormThreads / 64];
+                                                                   int64_t total_strips) {
     const int m = blockIdx.y;
-    for (int64_t tg = blockIdx.x; tg < total_tiles; tg += gridDim.x) {
-        const BatchProduct& q = P[batch_find(P, count, tg, false)];
-        const int64_t t = tg - q.tile_base, ti = t / q.bdim, tj = t - (t / q.bdim) * q.bdim;
-        const int64_t n = q.n, leaf = q.leaf;
-        const float* __restrict__ x = m == 0 ? q.a : q.b;
-        const int64_t rows = (ti * leaf + leaf < n ? leaf : n - ti * leaf);
-        const int64_t cols = (tj * leaf + leaf < n ? leaf : n - tj * leaf);
-        double acc = 0.0;
-        if (q.vec && cols == leaf) {  // whole rows of float4
-            const int64_t c4n = leaf / 4;
-            for (int64_t e = threadIdx.x; e < rows * c4n; e += kNormThreads) {
-                const int64_t r = ti * leaf + e / c4n, c = tj * leaf + 4 * (e % c4n);
-                const f4 v = *reinterpret_cast<const f4*>(x + r * n + c);
-                acc += double(v.x) * double(v.x) + double(v.y) * double(v.y) + double(v.z) * double(v.z) +
-                       double(v.w) * double(v.w);
-            }
-        } else {
-            for (int64_t e = threadIdx.x; e < rows * cols; e += kNormThreads) {
-                const int64_t r = ti * leaf + e / cols, c = tj * leaf + e % cols;
-                const double v = double(x[r * n + c]);
-                acc += v * v;
-            }
+    for (int64_t bg = blockIdx.x; bg < total_strips; bg += gridDim.x) {
+        const BatchProduct& q = P[batch_find(P, count, bg, kFindNorm)];
+        const int64_t b = bg - q.norm_base;
+        switch (q.leaf) {
+            case 32: batch_strip<32>(q, m, b); break;
+            case 64: batch_strip<64>(q, m, b); break;
+            default: batch_strip<128>(q, m, b); break;
         }
-        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-        if ((threadIdx.x & 63) == 0) partial[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < kNormThreads / 64; ++w) sum += partial[w];
-            const int64_t at = level_offset(q.lv) + ti * (int64_t(1) << q.lv) + tj;
-            q.spyr[m][at] = sum;
-            q.pyr[m][at] = sqrt(sum);
-        }
-        __syncthreads();
     }
 }
 
@@ -867,7 +866,7 @@ __global__ __launch_bounds__(kPyrThreads) void batch_pyramid_kernel(const BatchP
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_mask_kernel(const BatchProduct* __restrict__ P,
                                                                        int32_t count, int64_t total_blocks) {
     for (int64_t bg = blockIdx.x; bg < total_blocks; bg += gridDim.x) {
-        const BatchProduct& q = P[batch_find(P, count, bg, true)];
+        const BatchProduct& q = P[batch_find(P, count, bg, kFindMask)];
         const int64_t b = bg - q.mask_base;
         plan_mask_block<true, false>(q.pyr[0], q.pyr[1], q.bdim, q.lv, q.tau, q.masks, q.counts, q.bsums, b % q.nw,
                                      b / q.nw);
@@ -883,7 +882,7 @@ __global__ __launch_bounds__(kScanThreads) void batch_plan_scan_kernel(const Bat
 __global__ __launch_bounds__(256) void batch_plan_fill_kernel(const BatchProduct* __restrict__ P, int32_t count,
                                                               int64_t total_tiles) {
     for (int64_t tg = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); tg < total_tiles; tg += int64_t(gridDim.x) * 4) {
-        const BatchProduct& q = P[batch_find(P, count, tg, false)];
+        const BatchProduct& q = P[batch_find(P, count, tg, kFindTile)];
         plan_fill_wave(q.masks, q.counts, q.boffs, q.bdim, q.offsets, q.klist, tg - q.tile_base);
     }
 }
@@ -955,9 +954,10 @@ __global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_batch
 
 hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
                         const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
-                        int64_t total_mask_blocks, int num_cus, hipStream_t s) {
+                        int64_t total_mask_blocks, int64_t total_strips, int num_cus, hipStream_t s) {
     auto blocks = [](int64_t work, int64_t cap) { return unsigned(work < cap ? (work > 0 ? work : 1) : cap); };
-    batch_norms_kernel<<<dim3{blocks(total_tiles, 1 << 20), 2u, 1u}, kNormThreads, 0, s>>>(prods, count, total_tiles);
+    batch_norms_kernel<<<dim3{blocks(total_strips, 1 << 20), 2u, 1u}, kNormThreads, 0, s>>>(prods, count,
+                                                                                           total_strips);
     batch_pyramid_kernel<<<dim3{unsigned(count), 2u, 1u}, kPyrThreads, 0, s>>>(prods);
     batch_plan_mask_kernel<<<blocks(total_mask_blocks, 1 << 20), kPlanThreads, 0, s>>>(prods, count,
                                                                                        total_mask_blocks);
