@@ -18,7 +18,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 LIB = PKG / "libspamm.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "split.hip", CSRC / "learned.hip",
+SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "multiply_lowp.hip", CSRC / "split.hip", CSRC / "learned.hip",
            CSRC / "api.hip", CSRC / "api_tau.hip", CSRC / "api_batch.hip"]
 ARCH = "gfx950"
 

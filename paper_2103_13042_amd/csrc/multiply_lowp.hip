@@ -1,0 +1,222 @@
+// Reduced-precision leaf products (leaf 64, N a multiple of 128) from the split
+// operands of split.hip, on the macro-tile schedule of multiply_macro.hip.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "dma.h"
+#include "internal.h"
+
+namespace spamm {
+
+// ---------------------------------------------------------------------------
+// Reduced-precision leaf products (leaf 64, N a multiple of 128): the macro-tile
+// stream of the FP32 DMA kernel (multiply_macro.hip), with operands from the split pass: A rows
+// and Bt rows (columns of B) of 64 halves per leaf k-range, so an item is one
+// union k and a stage holds A rows [2I*64, 2I*64+128) and Bt rows
+// [2J*64, 2J*64+128), one plane (bf16) or two (FP16 hi and lo) each.
+//
+// Each wave computes the same 32x32 quadrant as in the FP32 kernel with
+// v_mfma_f32_32x32x16 (lane l takes k = 16 s + 8 (l >> 5) + 0..7 of row l & 31
+// of both operands: one 16-byte LDS read each).  FP16: per k-step the three
+// products hi*hi, hi*lo, lo*hi accumulate into one FP32 accumulator; the
+// result is scaled by 2^-(eA + eB) when stored.  Rows are 128 bytes in LDS;
+// 16-byte chunk c of row r sits at position c ^ (r & 7), which spreads the 8
+// rows a group of 8 lanes reads over all banks.
+template <int MODE>
+struct LowpGeom {
+    static constexpr int NP = MODE == kPrecF16x3 ? 2 : 1;  // planes per operand
+    static constexpr int PLANE = 128 * 64 * 2;             // 128 rows x 64 halves
+    static constexpr int STAGE = 2 * NP * PLANE;
+    static constexpr int S = MODE == kPrecF16x3 ? 2 : 3;   // stages
+    static constexpr int COPIES = 2 * NP;                  // per wave per item
+    static_assert(S * STAGE <= 160 * 1024, "LDS budget");
+};
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+template <int MODE>
+__global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
+    const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al, const uint16_t* __restrict__ Bh,
+    const uint16_t* __restrict__ Bl, const int32_t* __restrict__ exps, float* __restrict__ C, int64_t n,
+    int64_t bdim, int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix) {
+    using G = LowpGeom<MODE>;
+    constexpr int LEAF = 64, S = G::S;
+    __shared__ __attribute__((aligned(1024))) char lds[S * G::STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
+              qc = (wave >> 2) & 1;
+    const int ir = lane & 31, g = lane >> 5;
+
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t nm = mb * mb;
+    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
+    auto start_of = [&](int64_t gg) {
+        const int64_t target = gg * total;
+        int64_t lo = 0, hi = nm;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    };
+    const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
+    if (m_begin >= m_end) return;
+    const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]);
+    const float inv = MODE == kPrecF16x3 ? ldexpf(1.0f, -(exps[0] + exps[1])) : 1.0f;
+
+    const uint32_t* ip = items + uprefix[m_begin];
+    int64_t pp = 0;
+    uint32_t last = 0;
+    auto produce = [&]() -> uint32_t {
+        if (pp < nitems) last = ip[pp];
+        ++pp;
+        return last;
+    };
+
+    f16v acc;
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    };
+    auto store_macro = [&](int64_t m) {  // exactly kDmaStores stores per wave
+        const int64_t ti = 2 * (m / mb) + wa, tj = 2 * (m - (m / mb) * mb) + wb;
+        float* dst = C + (ti * LEAF + qr * 32 + 4 * g) * n + tj * LEAF + qc * 32 + ir;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[(8 * (r >> 2) + (r & 3)) * n] = acc[r] * inv;
+    };
+    // one 1 KiB copy per plane per wave: rows wave*8 .. wave*8+7 of the stage
+    auto copy_item = [&](uint32_t pi, int st) {
+        const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
+        const int rr = wave * 8 + (lane >> 3), c = (lane & 7) ^ (rr & 7);
+        char* sbase = lds + st * G::STAGE + wave * 1024;
+        const int64_t aoff = (2 * I * LEAF + rr) * n + kt * LEAF + 8 * c;
+        const int64_t boff = (2 * J * LEAF + rr) * n + kt * LEAF + 8 * c;
+        __builtin_amdgcn_global_load_lds(Ah + aoff, (__attribute__((address_space(3))) void*)(sbase), 16, 0, 0);
+        if (G::NP == 2)
+            __builtin_amdgcn_global_load_lds(Al + aoff, (__attribute__((address_space(3))) void*)(sbase + G::PLANE),
+                                             16, 0, 0);
+        __builtin_amdgcn_global_load_lds(Bh + boff,
+                                         (__attribute__((address_space(3))) void*)(sbase + G::NP * G::PLANE), 16, 0, 0);
+        if (G::NP == 2)
+            __builtin_amdgcn_global_load_lds(
+                Bl + boff, (__attribute__((address_space(3))) void*)(sbase + 3 * G::PLANE), 16, 0, 0);
+    };
+    auto compute = [&](int st) {
+        const char* sa = lds + st * G::STAGE;
+        const char* sb = sa + G::NP * G::PLANE;
+        const int ra = wa * 64 + qr * 32 + ir, rb = wb * 64 + qc * 32 + ir;
+        const char* arow = sa + ra * 128;
+        const char* brow = sb + rb * 128;
+        if (MODE == kPrecF16x3) {
+            // two k-steps of operands at a time (32 registers): the second
+            // pair's reads issue while the first pair's MFMAs execute
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                h8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int s4 = 2 * h + u;
+                    const int pa = ((2 * s4 + g) ^ (ra & 7)) * 16, pb = ((2 * s4 + g) ^ (rb & 7)) * 16;
+                    ah[u] = *reinterpret_cast<const h8*>(arow + pa);
+                    al[u] = *reinterpret_cast<const h8*>(arow + G::PLANE + pa);
+                    bh[u] = *reinterpret_cast<const h8*>(brow + pb);
+                    bl[u] = *reinterpret_cast<const h8*>(brow + G::PLANE + pb);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u], bh[u], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u], bl[u], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[u], bh[u], acc, 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            b8 av[4], bv[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int pa = ((2 * s4 + g) ^ (ra & 7)) * 16, pb = ((2 * s4 + g) ^ (rb & 7)) * 16;
+                av[s4] = *reinterpret_cast<const b8*>(arow + pa);
+                bv[s4] = *reinterpret_cast<const b8*>(brow + pb);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s4], bv[s4], acc, 0, 0, 0);
+        }
+    };
+
+    uint32_t f[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) f[i] = produce();
+#pragma unroll
+    for (int i = 0; i < S - 1; ++i) copy_item(f[i], i);
+    int64_t out_m = m_begin;
+    int ns[S];  // macro tiles stored in the last S-1 steps (ns[0]: this step)
+#pragma unroll
+    for (int i = 0; i < S; ++i) ns[i] = 0;
+    zero_acc();
+    for (int64_t it = 0; it < nitems; ++it) {
+        const uint32_t pi = f[0];
+        const int64_t m_it = int64_t(pi >> 23) * mb + ((pi >> 14) & 511);
+#pragma unroll
+        for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
+        ns[0] = 0;
+        while (out_m < m_it) {
+            store_macro(out_m);
+            zero_acc();
+            ++out_m;
+            ++ns[0];
+        }
+        int stores = 0;
+#pragma unroll
+        for (int i = 0; i < S - 1; ++i) stores += ns[i];
+        asm volatile("" ::: "memory");
+        wait_copies<(S - 2) * G::COPIES>(stores);
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        copy_item(f[S - 1], int((it + S - 1) % S));  // item it+S-1 -> the stage item it-1 used
+        if ((pi >> tile) & 1) compute(int(it % S));
+#pragma unroll
+        for (int i = 0; i < S - 1; ++i) f[i] = f[i + 1];
+        f[S - 1] = produce();
+    }
+    int64_t m_last = out_m;
+    while (m_last < m_end) {
+        store_macro(m_last);
+        zero_acc();
+        ++m_last;
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
+}
+
+hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64_t bdim, int precision,
+                                const uint32_t* items, const int32_t* uprefix, int num_cus, hipStream_t s) {
+    const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
+    const int64_t cap = ((nm + 7) / 8) * 8;
+    int64_t groups = int64_t(num_cus);
+    if (groups > cap) groups = cap;
+    groups = ((groups + 7) / 8) * 8;
+    static int scratch_bf16 = 0, scratch_f16 = 0;
+    if (precision == kPrecBf16) {
+        const hipError_t ce = check_no_scratch(multiply_lowp_kernel<kPrecBf16>, &scratch_bf16);
+        if (ce != hipSuccess) return ce;
+        multiply_lowp_kernel<kPrecBf16><<<unsigned(groups), kDmaThreads, 0, s>>>(
+            L.a_hi, L.a_lo, L.bt_hi, L.bt_lo, L.exps, c, n, bdim, mb, items, uprefix);
+    } else {
+        const hipError_t ce = check_no_scratch(multiply_lowp_kernel<kPrecF16x3>, &scratch_f16);
+        if (ce != hipSuccess) return ce;
+        multiply_lowp_kernel<kPrecF16x3><<<unsigned(groups), kDmaThreads, 0, s>>>(
+            L.a_hi, L.a_lo, L.bt_hi, L.bt_lo, L.exps, c, n, bdim, mb, items, uprefix);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spamm
