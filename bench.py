@@ -39,15 +39,24 @@ CSRC = ROOT / "paper_2103_13042_amd" / "csrc"
 CALIB_BYTES = 256 << 20  # device copy whose counter readings scale the HBM byte counters
 
 
-def multiply_kernel(n: int, leaf: int, precision: str = "fp32") -> tuple[str, Path]:
-    """Name and source file of the multiply kernel the timed step launches."""
+def multiply_kernel(n: int, leaf: int, precision: str = "fp32") -> tuple[str, list[Path]]:
+    """Name and source files (kernel file and the headers it includes) of the
+    multiply kernel the timed step launches."""
+    heads = [CSRC / "device.h", CSRC / "dma.h"]
     if precision != "fp32":
-        return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", CSRC / "multiply_macro.hip"
+        return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", [CSRC / "multiply_lowp.hip", *heads]
     if leaf == 64 and n % 128 == 0:
-        return "multiply_macro_dma_kernel", CSRC / "multiply_macro.hip"
+        return "multiply_macro_dma_kernel", [CSRC / "multiply_macro.hip", *heads]
     if leaf in (32, 64):
-        return f"multiply_macro_kernel<{leaf}", CSRC / "multiply_macro.hip"
-    return f"multiply_kernel<{leaf}", CSRC / "kernels.hip"
+        return f"multiply_macro_kernel<{leaf}", [CSRC / "multiply_macro.hip", *heads]
+    return f"multiply_kernel<{leaf}", [CSRC / "kernels.hip", CSRC / "device.h"]
+
+
+def sources_sha256(sources: list[Path]) -> str:
+    h = hashlib.sha256()
+    for src in sources:
+        h.update(src.read_bytes())
+    return h.hexdigest()
 
 
 def log(msg: str) -> None:
@@ -81,15 +90,15 @@ def parse_args():
     return ap.parse_args()
 
 
-def traffic_entry(kernel: str, source: Path, workload: str):
+def traffic_entry(kernel: str, sources: list[Path], workload: str):
     """HBM bytes per multiply launch from the committed counter summary, if it
-    was taken on this kernel, its current source and this workload (else None)."""
+    was taken on this kernel, its current sources and this workload (else None)."""
     try:
         rec = json.loads(TRAFFIC_FILE.read_text())
     except (OSError, ValueError):
         return None
-    sha = hashlib.sha256(source.read_bytes()).hexdigest()
-    if rec.get("source_sha256") != sha or rec.get("kernel") != kernel or rec.get("workload") != workload:
+    if rec.get("source_sha256") != sources_sha256(sources) or rec.get("kernel") != kernel \
+            or rec.get("workload") != workload:
         return None
     return rec
 
@@ -108,10 +117,10 @@ def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float,
     into profiles/multiply_traffic.json: per-dispatch KiB of the multiply kernel,
     each scaled by what the same counter reads for the CALIB_BYTES device copy.
     (Default workload and precision only.)"""
-    kernel, source = multiply_kernel(n, leaf)
+    kernel, sources = multiply_kernel(n, leaf)
     out = {"kernel": kernel, "workload": workload_name(n, leaf, tau),
-           "source": str(source.relative_to(ROOT)),
-           "source_sha256": hashlib.sha256(source.read_bytes()).hexdigest(), "commands": commands}
+           "sources": [str(src.relative_to(ROOT)) for src in sources],
+           "source_sha256": sources_sha256(sources), "commands": commands}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = list(_counter_rows(path, counter))
         ker = [v for name, v in rows if kernel in name]
