@@ -12,6 +12,19 @@ namespace spamm {
 constexpr int kUnionCost = 4;   // partition cost per union k of a macro tile
 constexpr int kMacroWrite = 2;  // partition cost per macro tile written
 
+// Item-level partition of the FP32 multiply.  Measured per-workgroup times
+// fit  t = a * items + b * kept + c * macro tiles  with a : b : c close to
+// 5 : 4 : 5 (an item's fixed cost of copies and barrier, the MFMA work of each
+// output tile that keeps the item's k, the store of a finished macro tile).
+constexpr int kItemCost = 5;
+constexpr int kKeptCost = 4;
+constexpr int kStoreCost = 5;
+// Workgroups of the split multiply and the per-workgroup partial slots of the
+// macro tiles split between workgroups (two per workgroup: the first and the
+// last macro tile it touches), 128 x 128 FP32 each.
+constexpr int kSplitMaxGroups = 256;
+constexpr int kSplitSlotFloats = 128 * 128;
+
 constexpr int kDmaThreads = 1024;
 constexpr int kDmaStores = 16;  // per wave per macro tile
 #ifndef SPAMM_DMA_KC
@@ -59,5 +72,52 @@ static hipError_t check_no_scratch(K kernel, int* state) {
     return *state == 1 ? hipSuccess : hipErrorInvalidDeviceFunction;
 }
 
+
+// Boundary gg of G in the item-level partition, wave-cooperative (every lane
+// returns the same value).  cprefix[m] is the cost of macro tiles 0..m-1
+// (kStoreCost + kItemCost per item + kKeptCost per kept tile of each item,
+// the store counted before the items); the boundary is the first item whose
+// cost before it reaches gg * total / G, as (macro tile, item index) with
+// uprefix[m] <= p < uprefix[m + 1], or (m, uprefix[m]) at a clean macro-tile
+// start (the end is (nm, uprefix[nm])).
+struct SplitBound {
+    int64_t m, p;
+};
+
+__device__ inline SplitBound split_bound(int64_t gg, int64_t G, int64_t nm, const int64_t* __restrict__ cprefix,
+                                         const int32_t* __restrict__ uprefix, const uint32_t* __restrict__ items) {
+    const int lane = threadIdx.x & 63;
+    if (gg <= 0) return {0, 0};
+    if (gg >= G) return {nm, int64_t(uprefix[nm])};
+    const int64_t T = gg * cprefix[nm] / G;
+    // largest m < nm with cprefix[m] <= T: 64-ary search, invariant
+    // cprefix[lo] <= T and the answer in [lo, hi)
+    int64_t lo = 0, hi = nm;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t c = lo + step * (lane + 1);
+        const bool le = lane < 63 && c < hi && cprefix[c] <= T;
+        const int cnt = __popcll(__ballot(le));  // monotone: lanes 0 .. cnt-1
+        lo += step * cnt;
+        hi = (lo + step < hi) ? lo + step : hi;
+    }
+    const int64_t m = lo, u0 = uprefix[m], u1 = uprefix[m + 1];
+    int64_t c0 = cprefix[m] + kStoreCost;  // cost before item u0
+    if (c0 >= T) return {m, u0};
+    for (int64_t base = u0; base < u1; base += 64) {
+        const int64_t i = base + lane;
+        const int cst = i < u1 ? kItemCost + kKeptCost * __popc(items[i] & 15u) : 0;
+        int incl = cst;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int up = __shfl_up(incl, o);
+            if (lane >= o) incl += up;
+        }
+        const uint64_t hit = __ballot(i < u1 && c0 + (incl - cst) >= T);
+        if (hit) return {m, base + __ffsll(static_cast<unsigned long long>(hit)) - 1};
+        c0 += __shfl(incl, 63);
+    }
+    return {m + 1, u1};
+}
 
 }  // namespace spamm

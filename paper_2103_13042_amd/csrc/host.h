@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "internal.h"
 #include "spamm.h"
 
 namespace spamm_host {
@@ -27,8 +28,8 @@ bool make_geom(int64_t n, int32_t leaf, Geom* g);
 
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
-    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix, mitems,
-        pairs, scalars, partials, total;
+    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mcost, mprefix,
+        cprefix, mitems, bounds, fix_slots, fix_slot_bytes, pairs, scalars, partials, total;
 };
 
 Layout make_layout(const Geom& g);
@@ -56,6 +57,8 @@ spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, dou
                           int32_t* offsets, int32_t* klist, int64_t* pairs, void* ws, hipStream_t s);
 // Multiply of the pairs of a plan into c (every tile of c is written): the
 // schedule the multiply kernel streams (workspace), then the multiply kernel.
+// The macro-tile schedule arrays of the workspace at ws.
+spamm::MacroSchedule macro_schedule(const Layout& L, void* ws);
 spamm_status enqueue_schedule(const Geom& g, const int32_t* offsets, const int32_t* klist, void* ws, hipStream_t s);
 spamm_status enqueue_multiply(const Geom& g, const float* a, const float* b, const int32_t* offsets,
                               const int32_t* klist, float* c, void* ws, hipStream_t s);

@@ -27,11 +27,12 @@ namespace spamm {
 constexpr int kMacThreads = 256;
 
 // One wave per macro tile: k-bitmaps of its four tiles (zero for tiles outside
-// the grid) and the size of their union.
+// the grid), the size of their union and the macro tile's partition cost
+// (kStoreCost + kItemCost per union k + kKeptCost per kept pair).
 __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restrict__ off,
                                                           const int32_t* __restrict__ klist, int64_t bdim, int64_t mb,
                                                           int nw, uint64_t* __restrict__ words,
-                                                          int32_t* __restrict__ ucount) {
+                                                          int32_t* __restrict__ ucount, int32_t* __restrict__ mcost) {
     __shared__ unsigned long long sw[4][4][16];  // [wave][tile][word]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t m = int64_t(blockIdx.x) * 4 + wave;
@@ -39,11 +40,13 @@ __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restr
     const int64_t I = m / mb, J = m - (m / mb) * mb;
     sw[wave][lane >> 4][lane & 15] = 0ull;
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): zeroing done before the ORs
+    int kept = 0;
     for (int ab = 0; ab < 4; ++ab) {
         const int64_t ti = 2 * I + (ab >> 1), tj = 2 * J + (ab & 1);
         if (ti >= bdim || tj >= bdim) continue;
         const int64_t t = ti * bdim + tj;
         const int32_t q0 = off[t], q1 = off[t + 1];
+        kept += q1 - q0;
         for (int32_t q = q0 + lane; q < q1; q += 64) {
             const int32_t k = klist[q];
             atomicOr(&sw[wave][ab][k >> 6], 1ull << (k & 63));
@@ -58,7 +61,62 @@ __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restr
     if (lane < 4 * nw) words[(m * 4 + lane / nw) * nw + lane % nw] = sw[wave][lane / nw][lane % nw];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane == 0) ucount[m] = cnt;
+    if (lane == 0) {
+        ucount[m] = cnt;
+        mcost[m] = kStoreCost + kItemCost * cnt + kKeptCost * kept;
+    }
+}
+
+// Exclusive prefixes of the union sizes (uprefix, int32, total at [nm]) and of
+// the macro-tile costs (cprefix, int64, total at [nm]), one workgroup.
+constexpr int kMacScanThreads = 1024;
+__global__ __launch_bounds__(kMacScanThreads) void macro_scan_kernel(const int32_t* __restrict__ ucount,
+                                                                     const int32_t* __restrict__ mcost, int64_t nm,
+                                                                     int32_t* __restrict__ uprefix,
+                                                                     int64_t* __restrict__ cprefix) {
+    __shared__ int64_t wsum[2][kMacScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t seg = (nm + kMacScanThreads - 1) / kMacScanThreads;
+    const int64_t b = tid * seg, e = (b + seg < nm ? b + seg : nm);
+    int64_t lu = 0, lc = 0;
+    for (int64_t t = b; t < e; ++t) {
+        lu += ucount[t];
+        lc += mcost[t];
+    }
+    int64_t iu = lu, ic = lc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t su = __shfl_up(iu, o), sc = __shfl_up(ic, o);
+        if (lane >= o) {
+            iu += su;
+            ic += sc;
+        }
+    }
+    if (lane == 63) {
+        wsum[0][wave] = iu;
+        wsum[1][wave] = ic;
+    }
+    __syncthreads();
+    int64_t ru = iu - lu, rc = ic - lc;
+    for (int w = 0; w < wave; ++w) {
+        ru += wsum[0][w];
+        rc += wsum[1][w];
+    }
+    for (int64_t t = b; t < e; ++t) {
+        uprefix[t] = int32_t(ru);
+        cprefix[t] = rc;
+        ru += ucount[t];
+        rc += mcost[t];
+    }
+    if (tid == kMacScanThreads - 1) {
+        int64_t tu = 0, tc = 0;
+        for (int w = 0; w < kMacScanThreads / 64; ++w) {
+            tu += wsum[0][w];
+            tc += wsum[1][w];
+        }
+        uprefix[nm] = int32_t(tu);
+        cprefix[nm] = tc;
+    }
 }
 
 // packed pair item: I << 23 | J << 14 | k << 4 | membership (bit a*2+b)
@@ -314,8 +372,9 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
 // ---------------------------------------------------------------------------
 // Leaf 64 with N a multiple of 128 (whole macro tiles, every access inside
 // the matrix): the same macro-tile stream, but tiles move from global memory
-// straight into LDS (global_load_lds_dwordx4) through four LDS stages, so three
-// items are in flight while one is multiplied and no registers stage the data.
+// straight into LDS (global_load_lds_dwordx4) through kDmaStages LDS stages of
+// one item (kDmaKC k) each, so the copies of the next items are in flight
+// while one is multiplied and no registers stage the data.
 //
 // Sixteen waves: wave w computes the 32x32 quadrant (w >> 3 & 1, w >> 2 & 1)
 // of output tile (w + (w >> 2)) & 3 of the macro tile.  Waves are dealt to the
@@ -324,22 +383,33 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
 // SIMDs whichever of the four tiles keep its k.
 //
 // LDS rows are stored without padding; 16-byte chunks are XOR-swizzled so the
-// MFMA operand reads are free of bank conflicts: A row r keeps global chunk c
-// at position c ^ ((r >> 1) & 7), B row r at position c ^ (8 * ((r >> 4) & 1)).
+// MFMA operand reads are free of bank conflicts.
 //
 // Completion of the copies is tracked by hand with s_waitcnt vmcnt: every
-// wave issues exactly 2 copies per item and exactly 16 stores per finished
-// output quadrant (no access is predicated), so the number of memory
-// operations issued after the copies of item it is known.  Empty asm
-// statements with a memory clobber keep the compiler from moving LDS or
+// wave issues exactly kDmaCopies copies per item and exactly kDmaStores
+// stores per finished macro tile (no access is predicated), so the number of
+// memory operations issued after the copies of item it is known; a split
+// macro tile (below) waits for all of the wave's operations instead.  Empty
+// asm statements with a memory clobber keep the compiler from moving LDS or
 // global accesses across the hand-placed waits and the barrier.
+//
+// Work split: workgroup g takes the items between boundaries g and g+1 of the
+// item-level cost partition (split_bound), so a macro tile may be shared by
+// consecutive workgroups.  Each sharer writes its partial sums to its own
+// slot instead of C; macro_fixup_kernel, launched next on the stream, adds the
+// partials of every shared tile in workgroup order and writes C.
 __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
-    int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix) {
+    int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix,
+    const int64_t* __restrict__ cprefix, int64_t* __restrict__ bounds, float* __restrict__ fix_slots) {
     constexpr int LEAF = 64, KC = kDmaKC, NCH = LEAF / KC, SPC = KC / 2;
-    constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;  // 16 KiB each
+    constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;
     constexpr int STAGE_BYTES = ABYTES + BBYTES;
-    __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES];
+    // one LDS object (the stages, then the two partition boundaries): a second
+    // __shared__ array makes the compiler wait for every outstanding copy
+    // before each LDS read
+    __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES + 4 * sizeof(int64_t)];
+    int64_t(*sbound)[2] = reinterpret_cast<int64_t(*)[2]>(lds + kDmaStages * STAGE_BYTES);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // waves w, w+4, w+8, w+12 share a SIMD: give them different output tiles
@@ -354,27 +424,29 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     const int64_t bid = blockIdx.x;
     const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
     const int64_t nm = mb * mb;
-    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
-    auto start_of = [&](int64_t gg) {
-        const int64_t target = gg * total;
-        int64_t lo = 0, hi = nm;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
-                hi = mid;
-            else
-                lo = mid + 1;
+    // boundaries lg and lg+1, one wave each
+    if (wave < 2) {
+        const SplitBound sbd = split_bound(lg + wave, groups, nm, cprefix, uprefix, items);
+        if (lane == 0) {
+            sbound[wave][0] = sbd.m;
+            sbound[wave][1] = sbd.p;
         }
-        return lo;
-    };
-    const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
+    }
+    __syncthreads();
+    if (tid < 2) bounds[2 * lg + tid] = sbound[0][tid];  // for macro_fixup_kernel
+    const int64_t m_first = sbound[0][0], p_begin = sbound[0][1];
+    const int64_t m_next = sbound[1][0], p_end = sbound[1][1];
+    const bool has_items = p_begin < p_end;
+    const bool head_split = has_items && p_begin > uprefix[m_first];
+    const bool tail_split = has_items && m_next < nm && p_end > uprefix[m_next];
+    const int64_t m_begin = m_first, m_end = m_next + (tail_split ? 1 : 0);
     if (m_begin >= m_end) return;
-    const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]) * NCH;
 
     // this group's slice of the item list (wave-uniform); past the end the
     // last item repeats (a harmless reload)
-    const uint32_t* ip = items + uprefix[m_begin];
-    const int64_t npairs = int64_t(uprefix[m_end] - uprefix[m_begin]);
+    const uint32_t* ip = items + p_begin;
+    const int64_t npairs = p_end - p_begin;
+    const int64_t nitems = npairs * NCH;
     int64_t pp = 0;
     uint32_t last = 0;
     auto produce = [&]() -> uint32_t {
@@ -388,12 +460,26 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     };
-    // exactly kDmaStores stores per wave
-    auto store_macro = [&](int64_t m) {
-        const int64_t ti = 2 * (m / mb) + wa, tj = 2 * (m - (m / mb) * mb) + wb;
-        float* dst = C + (ti * LEAF + qr * 32 + 4 * g) * n + tj * LEAF + qc * 32 + ir;
+    // exactly kDmaStores stores per wave: the accumulators of finished macro
+    // tile m to C, or for a tile shared with other workgroups to this
+    // workgroup's slot (a 128 x 128 row-major tile; side 1 if this workgroup
+    // holds the tile's first item, the tile being its last, side 0 otherwise,
+    // the tile being its first)
+    auto store_macro = [&](int64_t m, bool shared) {
+        const int64_t I = m / mb, J = m - (m / mb) * mb;
+        float* base;
+        int64_t ld;
+        if (shared) {
+            const int side = p_begin <= int64_t(uprefix[m]) ? 1 : 0;
+            base = fix_slots + (lg * 2 + side) * int64_t(kSplitSlotFloats);
+            ld = 2 * LEAF;
+        } else {
+            base = C + 2 * I * LEAF * n + 2 * J * LEAF;
+            ld = n;
+        }
+        float* dst = base + (wa * LEAF + qr * 32 + 4 * g) * ld + wb * LEAF + qc * 32 + ir;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) dst[(8 * (r >> 2) + (r & 3)) * n] = acc[r];
+        for (int r = 0; r < 16; ++r) dst[(8 * (r >> 2) + (r & 3)) * ld] = acc[r];
     };
 
     // copies of item (pair item pi, chunk ch) into stage st: KC/32 A and KC/32
@@ -470,6 +556,14 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     int ns[S];  // macro tiles stored in the last S-1 steps (ns[0]: this step)
 #pragma unroll
     for (int i = 0; i < S; ++i) ns[i] = 0;
+    // finish macro tile out_m: its C tile, or this workgroup's partial sums of
+    // a shared tile (kDmaStores stores per wave either way)
+    auto finish = [&]() {
+        store_macro(out_m, (out_m == m_first && head_split) || (out_m == m_next && tail_split));
+        ++ns[0];
+        zero_acc();
+        ++out_m;
+    };
     zero_acc();
     for (int64_t it = 0; it < nitems; ++it) {
         const uint32_t pi = f[0];
@@ -477,12 +571,7 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
 #pragma unroll
         for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
         ns[0] = 0;
-        while (out_m < m_it) {
-            store_macro(out_m);
-            zero_acc();
-            ++out_m;
-            ++ns[0];
-        }
+        while (out_m < m_it) finish();
         int stores = 0;
 #pragma unroll
         for (int i = 0; i < S - 1; ++i) stores += ns[i];
@@ -509,42 +598,91 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
             f[S - 1] = produce();
         }
     }
-    int64_t m_last = out_m;
-    while (m_last < m_end) {
-        store_macro(m_last);
-        zero_acc();
-        ++m_last;
-    }
+    while (out_m < m_end) finish();
     __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
 }
 
-hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, uint64_t* words,
-                                 int32_t* ucount, int32_t* uprefix, uint32_t* items, hipStream_t s) {
+// One workgroup per interior boundary g = 1 .. G-1 of the split multiply
+// (bounds[2g], bounds[2g+1] = its macro tile and item position): if boundary
+// g lies inside macro tile M and boundary g-1 does not, M is shared by
+// workgroups g-1 .. hi (hi holds M's last item).  Their partial sums (slot
+// side 1 of workgroup g-1, side 0 of the others; empty workgroups skipped)
+// are added in that order and written to C.
+__global__ __launch_bounds__(kDmaThreads) void macro_fixup_kernel(float* __restrict__ C, int64_t n, int64_t mb,
+                                                                  const int32_t* __restrict__ uprefix,
+                                                                  const int64_t* __restrict__ bounds,
+                                                                  const float* __restrict__ fix_slots,
+                                                                  int64_t groups) {
+    constexpr int LEAF = 64;
+    const int tid = threadIdx.x;
+    const int64_t nm = mb * mb, gb = int64_t(blockIdx.x) + 1;
+    const int64_t m = bounds[2 * gb], p = bounds[2 * gb + 1];
+    if (m >= nm) return;
+    const int64_t u0 = uprefix[m], u1 = uprefix[m + 1];
+    if (p <= u0) return;                                         // a clean boundary
+    if (bounds[2 * gb - 2] == m && bounds[2 * gb - 1] > u0) return;  // tile handled by an earlier boundary
+    auto pos = [&](int64_t c) { return c >= groups ? int64_t(uprefix[nm]) : bounds[2 * c + 1]; };
+    // element e = tid + 1024 j of the 128 x 128 tile: row e / 128, column e % 128
+    constexpr int EL = (2 * LEAF * 2 * LEAF) / kDmaThreads;
+    float sum[EL];
+    {
+        const float* src = fix_slots + ((gb - 1) * 2 + 1) * int64_t(kSplitSlotFloats);
+#pragma unroll
+        for (int j = 0; j < EL; ++j) sum[j] = src[tid + j * kDmaThreads];
+    }
+    for (int64_t c = gb, pc = p; pc < u1; ++c) {
+        const int64_t pn = pos(c + 1);
+        if (pc < pn) {
+            const float* src = fix_slots + (c * 2) * int64_t(kSplitSlotFloats);
+#pragma unroll
+            for (int j = 0; j < EL; ++j) sum[j] += src[tid + j * kDmaThreads];
+        }
+        pc = pn;
+    }
+    const int64_t I = m / mb, J = m - (m / mb) * mb;
+    float* dst = C + 2 * I * LEAF * n + 2 * J * LEAF;
+#pragma unroll
+    for (int j = 0; j < EL; ++j) {
+        const int e = tid + j * kDmaThreads;
+        dst[(e / (2 * LEAF)) * n + e % (2 * LEAF)] = sum[j];
+    }
+}
+
+hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, const MacroSchedule& ms,
+                                 hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int nw = int((bdim + 63) / 64);
-    macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, words, ucount);
+    macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, ms.words, ms.ucount,
+                                                              ms.mcost);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_plan_scan(ucount, nm, uprefix, uprefix, nm, nullptr, s);
+    macro_scan_kernel<<<1, kMacScanThreads, 0, s>>>(ms.ucount, ms.mcost, nm, ms.uprefix, ms.cprefix);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    macro_items_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(words, uprefix, mb, nw, items);
+    macro_items_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(ms.words, ms.uprefix, mb, nw, ms.items);
     return hipGetLastError();
 }
 
 template <int LEAF>
 static hipError_t launch_macro_run(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
-                                   const uint32_t* items, const int32_t* uprefix, bool vec, int num_cus,
-                                   hipStream_t s) {
+                                   const MacroSchedule& ms, bool vec, int num_cus, hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int64_t cap = ((nm + 7) / 8) * 8;
     if (LEAF == 64 && vec && n % 128 == 0) {
+        if (!ms.bounds || !ms.fix_slots) return hipErrorInvalidValue;
         static int scratch_state = 0;
         const hipError_t ce = check_no_scratch(multiply_macro_dma_kernel, &scratch_state);
         if (ce != hipSuccess) return ce;
         int64_t groups = int64_t(num_cus);
         if (groups > cap) groups = cap;
         groups = ((groups + 7) / 8) * 8;
-        multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, bdim, mb, items, uprefix);
+        if (groups > kSplitMaxGroups) groups = kSplitMaxGroups;
+        multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, bdim, mb, ms.items, ms.uprefix,
+                                                                          ms.cprefix, ms.bounds, ms.fix_slots);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || groups < 2) return e;
+        macro_fixup_kernel<<<unsigned(groups - 1), kDmaThreads, 0, s>>>(c, n, mb, ms.uprefix, ms.bounds,
+                                                                        ms.fix_slots, groups);
         return hipGetLastError();
     }
     int64_t groups = int64_t(num_cus) * MacGeom<LEAF>::OCC;
@@ -552,19 +690,18 @@ static hipError_t launch_macro_run(const float* a, const float* b, float* c, int
     groups = ((groups + 7) / 8) * 8;
     if (vec)
         multiply_macro_kernel<LEAF, true>
-            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, items, uprefix);
+            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, ms.items, ms.uprefix);
     else
         multiply_macro_kernel<LEAF, false>
-            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, items, uprefix);
+            <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, ms.items, ms.uprefix);
     return hipGetLastError();
 }
 
 hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const uint32_t* items, const int32_t* uprefix, bool vec, int num_cus,
-                                 hipStream_t s) {
+                                 const MacroSchedule& ms, bool vec, int num_cus, hipStream_t s) {
     switch (leaf) {
-        case 32: return launch_macro_run<32>(a, b, c, n, bdim, items, uprefix, vec, num_cus, s);
-        case 64: return launch_macro_run<64>(a, b, c, n, bdim, items, uprefix, vec, num_cus, s);
+        case 32: return launch_macro_run<32>(a, b, c, n, bdim, ms, vec, num_cus, s);
+        case 64: return launch_macro_run<64>(a, b, c, n, bdim, ms, vec, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }

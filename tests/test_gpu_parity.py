@@ -256,6 +256,38 @@ def test_many_pairs_per_workgroup(n, leaf):
     assert rel <= REL_FRO, rel
 
 
+@pytest.mark.parametrize("kind", ["one_block", "scattered"])
+def test_macro_tiles_shared_between_workgroups(kind):
+    """Leaf 64, N a multiple of 128: the multiply splits its item list between
+    workgroups by cost, so one macro tile can be computed by several
+    workgroups whose partial sums are added by the last to arrive.
+    one_block: all the work sits in one 2x2 block of output tiles (A nonzero
+    in its first 128 rows, B in its first 128 columns), so that block is
+    shared by many workgroups with about one item each; scattered: random
+    tile-level sparsity, many blocks split between two workgroups.  Checked
+    against the oracle, and run twice for bitwise equality (the partials are
+    added in workgroup order, not arrival order)."""
+    rng = np.random.default_rng(31)
+    n, leaf, tau = 1024, 64, 1e-6
+    a, b = inputs.uniform_pm1(n, 41), inputs.uniform_pm1(n, 42)
+    if kind == "one_block":
+        a[128:, :] = 0.0
+        b[:, 128:] = 0.0
+    else:
+        bd = n // leaf
+        ka = np.kron(rng.random((bd, bd)) < 0.15, np.ones((leaf, leaf), dtype=bool))
+        kb = np.kron(rng.random((bd, bd)) < 0.15, np.ones((leaf, leaf), dtype=bool))
+        a = np.where(ka, a, 0.0).astype(np.float32)
+        b = np.where(kb, b, 0.0).astype(np.float32)
+    c_ref, count, _ = oracle.spamm(a, b, tau, leaf)
+    ga, gb = gpu(a), gpu(b)
+    c1, p1 = sp.multiply(ga, gb, tau, leaf)
+    c2, p2 = sp.multiply(ga, gb, tau, leaf)
+    assert p1 == p2 == count
+    assert torch.equal(c1, c2)
+    check_c(c1.cpu().numpy(), a, b, tau, leaf, c_ref=c_ref)
+
+
 def test_tau_above_every_product_gives_exact_zero():
     n, leaf = 700, 64
     a, b = inputs.uniform_pm1(n, 3), inputs.uniform_pm1(n, 4)
