@@ -71,11 +71,9 @@ Layout make_layout(const Geom& g) {
     const size_t nm = size_t((g.bdim + 1) / 2) * size_t((g.bdim + 1) / 2);
     L.mwords = take(sizeof(uint64_t) * nm * 4 * size_t(g.nwords));
     L.mcount = take(sizeof(int32_t) * nm);
-    L.mcost = take(sizeof(int32_t) * nm);
     L.mprefix = take(sizeof(int32_t) * (nm + 1));
-    L.cprefix = take(sizeof(int64_t) * (nm + 1));
     L.mitems = take(sizeof(uint32_t) * nm * size_t(g.bdim));
-    L.bounds = take(sizeof(int64_t) * 2 * spamm::kSplitMaxGroups);
+    L.bounds = take(sizeof(int64_t) * 4 * spamm::kSplitMaxGroups);
     // partial sums of shared macro tiles: the leaf-64 LDS-DMA kernel only,
     // two slots per workgroup (at most one workgroup per 2x2 macro tile)
     const bool dma = g.leaf == 64 && g.n % 128 == 0;
@@ -183,9 +181,7 @@ spamm::MacroSchedule macro_schedule(const Layout& L, void* ws) {
     spamm::MacroSchedule ms{};
     ms.words = at<uint64_t>(ws, L.mwords);
     ms.ucount = at<int32_t>(ws, L.mcount);
-    ms.mcost = at<int32_t>(ws, L.mcost);
     ms.uprefix = at<int32_t>(ws, L.mprefix);
-    ms.cprefix = at<int64_t>(ws, L.cprefix);
     ms.items = at<uint32_t>(ws, L.mitems);
     ms.bounds = at<int64_t>(ws, L.bounds);
     ms.fix_slots = L.fix_slot_bytes ? at<float>(ws, L.fix_slots) : nullptr;
@@ -204,8 +200,8 @@ spamm_status enqueue_multiply(const Geom& g, const float* a, const float* b, con
     const bool vec = (g.n % 4) == 0 && aligned16(a) && aligned16(b);
     const Layout L = make_layout(g);
     if (g.leaf == 32 || g.leaf == 64)
-        return hip_check(spamm::launch_macro_multiply(a, b, c, g.n, g.leaf, g.bdim, macro_schedule(L, ws), vec,
-                                                      device_cus(), s),
+        return hip_check(spamm::launch_macro_multiply(a, b, c, g.n, g.leaf, g.bdim, offsets, macro_schedule(L, ws),
+                                                      vec, device_cus(), s),
                          "macro multiply kernel");
     return hip_check(spamm::launch_multiply(a, b, c, g.n, g.leaf, g.bdim, offsets, klist,
                                             at<int32_t>(ws, L.pair_scratch), vec, device_cus(), s),

@@ -73,36 +73,52 @@ static hipError_t check_no_scratch(K kernel, int* state) {
 }
 
 
+// Modelled cost of the macro tiles before m (row-major), bdim = 2 mb even:
+// kStoreCost per tile + kItemCost per union k (uprefix) + kKeptCost per kept
+// pair, the pairs of the tiles before m read off the plan's offsets (all tile
+// rows above the macro row, and the first 2J tiles of its two tile rows).
+__device__ inline int64_t macro_cost_before(int64_t m, int64_t mb, const int32_t* __restrict__ uprefix,
+                                            const int32_t* __restrict__ offsets) {
+    const int64_t bdim = 2 * mb;
+    int64_t kept;
+    if (m >= mb * mb) {
+        kept = offsets[bdim * bdim];
+    } else {
+        const int64_t I = m / mb, J = m - (m / mb) * mb, r0 = 2 * I * bdim;
+        kept = int64_t(offsets[r0 + 2 * J]) + offsets[r0 + bdim + 2 * J] - offsets[r0 + bdim];
+    }
+    return kStoreCost * m + kItemCost * int64_t(uprefix[m]) + kKeptCost * kept;
+}
+
 // Boundary gg of G in the item-level partition, wave-cooperative (every lane
-// returns the same value).  cprefix[m] is the cost of macro tiles 0..m-1
-// (kStoreCost + kItemCost per item + kKeptCost per kept tile of each item,
-// the store counted before the items); the boundary is the first item whose
-// cost before it reaches gg * total / G, as (macro tile, item index) with
-// uprefix[m] <= p < uprefix[m + 1], or (m, uprefix[m]) at a clean macro-tile
-// start (the end is (nm, uprefix[nm])).
+// returns the same value): the first item whose modelled cost before it
+// reaches gg * total / G (the store of a macro tile counted before its items),
+// as (macro tile m, item index p) with uprefix[m] <= p < uprefix[m + 1], or
+// (m, uprefix[m]) at a clean macro-tile start (the end is (nm, uprefix[nm])).
 struct SplitBound {
     int64_t m, p;
 };
 
-__device__ inline SplitBound split_bound(int64_t gg, int64_t G, int64_t nm, const int64_t* __restrict__ cprefix,
-                                         const int32_t* __restrict__ uprefix, const uint32_t* __restrict__ items) {
+__device__ inline SplitBound split_bound(int64_t gg, int64_t G, int64_t mb, const int32_t* __restrict__ uprefix,
+                                         const int32_t* __restrict__ offsets, const uint32_t* __restrict__ items) {
     const int lane = threadIdx.x & 63;
+    const int64_t nm = mb * mb;
     if (gg <= 0) return {0, 0};
     if (gg >= G) return {nm, int64_t(uprefix[nm])};
-    const int64_t T = gg * cprefix[nm] / G;
-    // largest m < nm with cprefix[m] <= T: 64-ary search, invariant
-    // cprefix[lo] <= T and the answer in [lo, hi)
+    const int64_t T = gg * macro_cost_before(nm, mb, uprefix, offsets) / G;
+    // largest m < nm with cost_before(m) <= T: 64-ary search, invariant
+    // cost_before(lo) <= T and the answer in [lo, hi)
     int64_t lo = 0, hi = nm;
     while (hi - lo > 1) {
         const int64_t step = (hi - lo + 63) / 64;
         const int64_t c = lo + step * (lane + 1);
-        const bool le = lane < 63 && c < hi && cprefix[c] <= T;
+        const bool le = lane < 63 && c < hi && macro_cost_before(c, mb, uprefix, offsets) <= T;
         const int cnt = __popcll(__ballot(le));  // monotone: lanes 0 .. cnt-1
         lo += step * cnt;
         hi = (lo + step < hi) ? lo + step : hi;
     }
     const int64_t m = lo, u0 = uprefix[m], u1 = uprefix[m + 1];
-    int64_t c0 = cprefix[m] + kStoreCost;  // cost before item u0
+    int64_t c0 = macro_cost_before(m, mb, uprefix, offsets) + kStoreCost;  // cost before item u0
     if (c0 >= T) return {m, u0};
     for (int64_t base = u0; base < u1; base += 64) {
         const int64_t i = base + lane;

@@ -28,8 +28,8 @@ bool make_geom(int64_t n, int32_t leaf, Geom* g);
 
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
-    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mcost, mprefix,
-        cprefix, mitems, bounds, fix_slots, fix_slot_bytes, pairs, scalars, partials, total;
+    size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix,
+        mitems, bounds, fix_slots, fix_slot_bytes, pairs, scalars, partials, total;
 };
 
 Layout make_layout(const Geom& g);

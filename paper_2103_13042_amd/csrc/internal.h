@@ -62,18 +62,16 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
 
 // Multiply on 2x2 macro tiles (leaf 32 and 64), in two steps.  Schedule:
 // per-macro-tile k bitmaps into words [mb*mb*4*nwords], union sizes into
-// ucount [mb*mb] and partition costs into mcost [mb*mb], their exclusive
-// prefixes into uprefix [mb*mb + 1] (int32) and cprefix [mb*mb + 1] (int64),
-// and the union k lists as packed items into items [<= mb*mb*bdim].
-// Multiply: the persistent kernel over that schedule; the leaf-64 LDS-DMA
-// kernel also writes its workgroups' partition boundaries to bounds
-// [2 * kSplitMaxGroups] and the partial sums of macro tiles shared between
-// workgroups to fix_slots [kSplitMaxGroups * 2 * 128 * 128], which a second
-// kernel adds into C.
+// ucount [mb*mb], their exclusive prefix into uprefix [mb*mb + 1], and the
+// union k lists as packed items into items [<= mb*mb*bdim].  Multiply: the
+// persistent kernel over that schedule; the leaf-64 LDS-DMA kernel (which
+// also reads the plan's offsets for its cost model) writes four records per
+// workgroup to bounds [4 * kSplitMaxGroups] and the partial sums of macro
+// tiles shared between workgroups to fix_slots [kSplitMaxGroups * 2 * 128 *
+// 128], which a second kernel adds into C.
 struct MacroSchedule {
     uint64_t* words;
-    int32_t *ucount, *mcost, *uprefix;
-    int64_t* cprefix;
+    int32_t *ucount, *uprefix;
     uint32_t* items;
     int64_t* bounds;
     float* fix_slots;
@@ -81,7 +79,8 @@ struct MacroSchedule {
 hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, const MacroSchedule& ms,
                                  hipStream_t s);
 hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const MacroSchedule& ms, bool vec, int num_cus, hipStream_t s);
+                                 const int32_t* offsets, const MacroSchedule& ms, bool vec, int num_cus,
+                                 hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Learned threshold (learned.hip).

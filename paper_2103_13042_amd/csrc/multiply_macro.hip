@@ -27,12 +27,11 @@ namespace spamm {
 constexpr int kMacThreads = 256;
 
 // One wave per macro tile: k-bitmaps of its four tiles (zero for tiles outside
-// the grid), the size of their union and the macro tile's partition cost
-// (kStoreCost + kItemCost per union k + kKeptCost per kept pair).
+// the grid) and the size of their union.
 __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restrict__ off,
                                                           const int32_t* __restrict__ klist, int64_t bdim, int64_t mb,
                                                           int nw, uint64_t* __restrict__ words,
-                                                          int32_t* __restrict__ ucount, int32_t* __restrict__ mcost) {
+                                                          int32_t* __restrict__ ucount) {
     __shared__ unsigned long long sw[4][4][16];  // [wave][tile][word]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t m = int64_t(blockIdx.x) * 4 + wave;
@@ -40,13 +39,11 @@ __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restr
     const int64_t I = m / mb, J = m - (m / mb) * mb;
     sw[wave][lane >> 4][lane & 15] = 0ull;
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): zeroing done before the ORs
-    int kept = 0;
     for (int ab = 0; ab < 4; ++ab) {
         const int64_t ti = 2 * I + (ab >> 1), tj = 2 * J + (ab & 1);
         if (ti >= bdim || tj >= bdim) continue;
         const int64_t t = ti * bdim + tj;
         const int32_t q0 = off[t], q1 = off[t + 1];
-        kept += q1 - q0;
         for (int32_t q = q0 + lane; q < q1; q += 64) {
             const int32_t k = klist[q];
             atomicOr(&sw[wave][ab][k >> 6], 1ull << (k & 63));
@@ -61,62 +58,7 @@ __global__ __launch_bounds__(256) void macro_words_kernel(const int32_t* __restr
     if (lane < 4 * nw) words[(m * 4 + lane / nw) * nw + lane % nw] = sw[wave][lane / nw][lane % nw];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane == 0) {
-        ucount[m] = cnt;
-        mcost[m] = kStoreCost + kItemCost * cnt + kKeptCost * kept;
-    }
-}
-
-// Exclusive prefixes of the union sizes (uprefix, int32, total at [nm]) and of
-// the macro-tile costs (cprefix, int64, total at [nm]), one workgroup.
-constexpr int kMacScanThreads = 1024;
-__global__ __launch_bounds__(kMacScanThreads) void macro_scan_kernel(const int32_t* __restrict__ ucount,
-                                                                     const int32_t* __restrict__ mcost, int64_t nm,
-                                                                     int32_t* __restrict__ uprefix,
-                                                                     int64_t* __restrict__ cprefix) {
-    __shared__ int64_t wsum[2][kMacScanThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t seg = (nm + kMacScanThreads - 1) / kMacScanThreads;
-    const int64_t b = tid * seg, e = (b + seg < nm ? b + seg : nm);
-    int64_t lu = 0, lc = 0;
-    for (int64_t t = b; t < e; ++t) {
-        lu += ucount[t];
-        lc += mcost[t];
-    }
-    int64_t iu = lu, ic = lc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t su = __shfl_up(iu, o), sc = __shfl_up(ic, o);
-        if (lane >= o) {
-            iu += su;
-            ic += sc;
-        }
-    }
-    if (lane == 63) {
-        wsum[0][wave] = iu;
-        wsum[1][wave] = ic;
-    }
-    __syncthreads();
-    int64_t ru = iu - lu, rc = ic - lc;
-    for (int w = 0; w < wave; ++w) {
-        ru += wsum[0][w];
-        rc += wsum[1][w];
-    }
-    for (int64_t t = b; t < e; ++t) {
-        uprefix[t] = int32_t(ru);
-        cprefix[t] = rc;
-        ru += ucount[t];
-        rc += mcost[t];
-    }
-    if (tid == kMacScanThreads - 1) {
-        int64_t tu = 0, tc = 0;
-        for (int w = 0; w < kMacScanThreads / 64; ++w) {
-            tu += wsum[0][w];
-            tc += wsum[1][w];
-        }
-        uprefix[nm] = int32_t(tu);
-        cprefix[nm] = tc;
-    }
+    if (lane == 0) ucount[m] = cnt;
 }
 
 // packed pair item: I << 23 | J << 14 | k << 4 | membership (bit a*2+b)
@@ -401,14 +343,14 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
 __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
     int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix,
-    const int64_t* __restrict__ cprefix, int64_t* __restrict__ bounds, float* __restrict__ fix_slots) {
+    const int32_t* __restrict__ offsets, int64_t* __restrict__ bounds, float* __restrict__ fix_slots) {
     constexpr int LEAF = 64, KC = kDmaKC, NCH = LEAF / KC, SPC = KC / 2;
     constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;
     constexpr int STAGE_BYTES = ABYTES + BBYTES;
     // one LDS object (the stages, then the two partition boundaries): a second
     // __shared__ array makes the compiler wait for every outstanding copy
     // before each LDS read
-    __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES + 4 * sizeof(int64_t)];
+    __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES + 6 * sizeof(int64_t)];
     int64_t(*sbound)[2] = reinterpret_cast<int64_t(*)[2]>(lds + kDmaStages * STAGE_BYTES);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -424,21 +366,32 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     const int64_t bid = blockIdx.x;
     const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
     const int64_t nm = mb * mb;
-    // boundaries lg and lg+1, one wave each
-    if (wave < 2) {
-        const SplitBound sbd = split_bound(lg + wave, groups, nm, cprefix, uprefix, items);
+    // boundaries lg, lg+1 and lg-1, one wave each
+    if (wave < 3) {
+        const SplitBound sbd = split_bound(wave < 2 ? lg + wave : lg - 1, groups, mb, uprefix, offsets, items);
         if (lane == 0) {
             sbound[wave][0] = sbd.m;
             sbound[wave][1] = sbd.p;
         }
     }
     __syncthreads();
-    if (tid < 2) bounds[2 * lg + tid] = sbound[0][tid];  // for macro_fixup_kernel
     const int64_t m_first = sbound[0][0], p_begin = sbound[0][1];
     const int64_t m_next = sbound[1][0], p_end = sbound[1][1];
     const bool has_items = p_begin < p_end;
     const bool head_split = has_items && p_begin > uprefix[m_first];
     const bool tail_split = has_items && m_next < nm && p_end > uprefix[m_next];
+    // record for macro_fixup_kernel: boundary lg; the macro tile it opens
+    // for sharing (boundary lg lies inside it and boundary lg-1 does not), or
+    // -1; and lg if this workgroup then holds the rest of that tile (it is
+    // the last of the two contributors), else -1
+    if (tid < 4) {
+        const bool inside = m_first < nm && p_begin > uprefix[m_first];
+        const bool opens = inside && !(sbound[2][0] == m_first && sbound[2][1] > uprefix[m_first]);
+        const int64_t v = tid < 2    ? sbound[0][tid]
+                          : tid == 2 ? (opens ? m_first : int64_t(-1))
+                                     : (opens && has_items && p_end >= uprefix[m_first + 1] ? lg : int64_t(-1));
+        bounds[4 * lg + tid] = v;
+    }
     const int64_t m_begin = m_first, m_end = m_next + (tail_split ? 1 : 0);
     if (m_begin >= m_end) return;
 
@@ -602,42 +555,47 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
 }
 
-// One workgroup per interior boundary g = 1 .. G-1 of the split multiply
-// (bounds[2g], bounds[2g+1] = its macro tile and item position): if boundary
-// g lies inside macro tile M and boundary g-1 does not, M is shared by
-// workgroups g-1 .. hi (hi holds M's last item).  Their partial sums (slot
-// side 1 of workgroup g-1, side 0 of the others; empty workgroups skipped)
-// are added in that order and written to C.
+// One workgroup per interior boundary g = 1 .. G-1 of the split multiply,
+// from the records the multiply kernel left in bounds[4g ..]: (macro tile,
+// item position) of boundary g, the shared macro tile M boundary g opens (or
+// -1) and M's last contributor (or -1: found here from the later
+// boundaries).  M's contributors are workgroups g-1 (slot side 1), g, g+1, ...
+// (side 0; those with empty ranges skipped); their partial sums are added in
+// that order and written to C.
 __global__ __launch_bounds__(kDmaThreads) void macro_fixup_kernel(float* __restrict__ C, int64_t n, int64_t mb,
                                                                   const int32_t* __restrict__ uprefix,
                                                                   const int64_t* __restrict__ bounds,
                                                                   const float* __restrict__ fix_slots,
                                                                   int64_t groups) {
     constexpr int LEAF = 64;
-    const int tid = threadIdx.x;
-    const int64_t nm = mb * mb, gb = int64_t(blockIdx.x) + 1;
-    const int64_t m = bounds[2 * gb], p = bounds[2 * gb + 1];
-    if (m >= nm) return;
-    const int64_t u0 = uprefix[m], u1 = uprefix[m + 1];
-    if (p <= u0) return;                                         // a clean boundary
-    if (bounds[2 * gb - 2] == m && bounds[2 * gb - 1] > u0) return;  // tile handled by an earlier boundary
-    auto pos = [&](int64_t c) { return c >= groups ? int64_t(uprefix[nm]) : bounds[2 * c + 1]; };
     // element e = tid + 1024 j of the 128 x 128 tile: row e / 128, column e % 128
     constexpr int EL = (2 * LEAF * 2 * LEAF) / kDmaThreads;
+    const int tid = threadIdx.x;
+    const int64_t nm = mb * mb, gb = int64_t(blockIdx.x) + 1;
+    const int64_t m = bounds[4 * gb + 2], last = bounds[4 * gb + 3];
+    if (m < 0) return;
+    auto slot = [&](int64_t c, int side) { return fix_slots + (c * 2 + side) * int64_t(kSplitSlotFloats); };
     float sum[EL];
-    {
-        const float* src = fix_slots + ((gb - 1) * 2 + 1) * int64_t(kSplitSlotFloats);
+    if (last >= 0) {  // two contributors, gb-1 and gb
+        const float* s0 = slot(gb - 1, 1);
+        const float* s1 = slot(gb, 0);
 #pragma unroll
-        for (int j = 0; j < EL; ++j) sum[j] = src[tid + j * kDmaThreads];
-    }
-    for (int64_t c = gb, pc = p; pc < u1; ++c) {
-        const int64_t pn = pos(c + 1);
-        if (pc < pn) {
-            const float* src = fix_slots + (c * 2) * int64_t(kSplitSlotFloats);
+        for (int j = 0; j < EL; ++j) sum[j] = s0[tid + j * kDmaThreads] + s1[tid + j * kDmaThreads];
+    } else {  // gb-1, then the non-empty ones of gb .. the one holding the tile's last item
+        const float* s0 = slot(gb - 1, 1);
 #pragma unroll
-            for (int j = 0; j < EL; ++j) sum[j] += src[tid + j * kDmaThreads];
+        for (int j = 0; j < EL; ++j) sum[j] = s0[tid + j * kDmaThreads];
+        auto pos = [&](int64_t c) { return c >= groups ? int64_t(uprefix[nm]) : bounds[4 * c + 1]; };
+        const int64_t u1 = uprefix[m + 1];
+        for (int64_t c = gb, pc = pos(gb); pc < u1; ++c) {
+            const int64_t pn = pos(c + 1);
+            if (pc < pn) {
+                const float* sc = slot(c, 0);
+#pragma unroll
+                for (int j = 0; j < EL; ++j) sum[j] += sc[tid + j * kDmaThreads];
+            }
+            pc = pn;
         }
-        pc = pn;
     }
     const int64_t I = m / mb, J = m - (m / mb) * mb;
     float* dst = C + 2 * I * LEAF * n + 2 * J * LEAF;
@@ -652,12 +610,10 @@ hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, i
                                  hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int nw = int((bdim + 63) / 64);
-    macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, ms.words, ms.ucount,
-                                                              ms.mcost);
+    macro_words_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, mb, nw, ms.words, ms.ucount);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    macro_scan_kernel<<<1, kMacScanThreads, 0, s>>>(ms.ucount, ms.mcost, nm, ms.uprefix, ms.cprefix);
-    e = hipGetLastError();
+    e = launch_plan_scan(ms.ucount, nm, ms.uprefix, ms.uprefix, nm, nullptr, s);
     if (e != hipSuccess) return e;
     macro_items_kernel<<<unsigned((nm + 3) / 4), 256, 0, s>>>(ms.words, ms.uprefix, mb, nw, ms.items);
     return hipGetLastError();
@@ -665,7 +621,8 @@ hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, i
 
 template <int LEAF>
 static hipError_t launch_macro_run(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
-                                   const MacroSchedule& ms, bool vec, int num_cus, hipStream_t s) {
+                                   const int32_t* offsets, const MacroSchedule& ms, bool vec, int num_cus,
+                                   hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int64_t cap = ((nm + 7) / 8) * 8;
     if (LEAF == 64 && vec && n % 128 == 0) {
@@ -678,7 +635,7 @@ static hipError_t launch_macro_run(const float* a, const float* b, float* c, int
         groups = ((groups + 7) / 8) * 8;
         if (groups > kSplitMaxGroups) groups = kSplitMaxGroups;
         multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, bdim, mb, ms.items, ms.uprefix,
-                                                                          ms.cprefix, ms.bounds, ms.fix_slots);
+                                                                          offsets, ms.bounds, ms.fix_slots);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess || groups < 2) return e;
         macro_fixup_kernel<<<unsigned(groups - 1), kDmaThreads, 0, s>>>(c, n, mb, ms.uprefix, ms.bounds,
@@ -698,10 +655,11 @@ static hipError_t launch_macro_run(const float* a, const float* b, float* c, int
 }
 
 hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
-                                 const MacroSchedule& ms, bool vec, int num_cus, hipStream_t s) {
+                                 const int32_t* offsets, const MacroSchedule& ms, bool vec, int num_cus,
+                                 hipStream_t s) {
     switch (leaf) {
-        case 32: return launch_macro_run<32>(a, b, c, n, bdim, ms, vec, num_cus, s);
-        case 64: return launch_macro_run<64>(a, b, c, n, bdim, ms, vec, num_cus, s);
+        case 32: return launch_macro_run<32>(a, b, c, n, bdim, offsets, ms, vec, num_cus, s);
+        case 64: return launch_macro_run<64>(a, b, c, n, bdim, offsets, ms, vec, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }
