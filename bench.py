@@ -45,8 +45,8 @@ def multiply_kernel(n: int, leaf: int, precision: str = "fp32") -> tuple[str, li
     heads = [CSRC / "device.h", CSRC / "dma.h"]
     if precision != "fp32":
         return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", [CSRC / "multiply_lowp.hip", *heads]
-    if leaf == 64 and n % 128 == 0:
-        return "multiply_macro_dma_kernel", [CSRC / "multiply_macro.hip", *heads]
+    if leaf == 64 and n % 128 == 0:  # the launch is two kernels: the multiply, then the split-tile fixup
+        return "multiply_macro_dma_kernel + macro_fixup_kernel", [CSRC / "multiply_macro.hip", *heads]
     if leaf in (32, 64):
         return f"multiply_macro_kernel<{leaf}", [CSRC / "multiply_macro.hip", *heads]
     return f"multiply_kernel<{leaf}", [CSRC / "kernels.hip", CSRC / "device.h"]
@@ -114,25 +114,25 @@ def _counter_rows(path: str, counter: str):
 
 def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float, commands: list[str]) -> int:
     """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE)
-    into profiles/multiply_traffic.json: per-dispatch KiB of the multiply kernel,
-    each scaled by what the same counter reads for the CALIB_BYTES device copy.
-    (Default workload and precision only.)"""
+    into profiles/multiply_traffic.json: per-dispatch KiB of the multiply launch
+    (the sum over its kernels), each scaled by what the same counter reads for
+    the CALIB_BYTES device copy.  (Default workload and precision only.)"""
     kernel, sources = multiply_kernel(n, leaf)
     out = {"kernel": kernel, "workload": workload_name(n, leaf, tau),
            "sources": [str(src.relative_to(ROOT)) for src in sources],
            "source_sha256": sources_sha256(sources), "commands": commands}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = list(_counter_rows(path, counter))
-        ker = [v for name, v in rows if kernel in name]
+        parts = [[v for name, v in rows if part in name] for part in kernel.split(" + ")]
         copies = [v for name, v in rows if "copyBuffer" in name]
-        if not ker or not copies:
+        if not all(parts) or not copies:
             print(f"{path}: no {counter} rows for {kernel} or the calibration copy", file=sys.stderr)
             return 1
         calib = max(copies)  # the CALIB_BYTES copy is the largest copy dispatch
         scale = (CALIB_BYTES / 1024.0) / calib
         key = counter.split("_")[0].lower()
-        out[f"{key}_kib_per_dispatch"] = float(np.mean(ker))
-        out[f"{key}_dispatches"] = len(ker)
+        out[f"{key}_kib_per_dispatch"] = float(sum(np.mean(p) for p in parts))
+        out[f"{key}_dispatches"] = min(len(p) for p in parts)
         out[f"{key}_calib_kib"] = calib
         out[f"{key}_scale"] = scale
     out["hbm_bytes_per_launch"] = round(1024.0 * (out["fetch_kib_per_dispatch"] * out["fetch_scale"]
