@@ -39,10 +39,15 @@ CSRC = ROOT / "paper_2103_13042_amd" / "csrc"
 CALIB_BYTES = 256 << 20  # device copy whose counter readings scale the HBM byte counters
 
 
-def multiply_kernel(n: int, leaf: int, precision: str = "fp32") -> tuple[str, list[Path]]:
+F16X3_STAGED_PAIRS_PER_TILE = 25  # the library's choice between the two FP16 hi+lo forms
+
+
+def multiply_kernel(n: int, leaf: int, precision: str = "fp32", f16x3_staged: bool = False) -> tuple[str, list[Path]]:
     """Name and source files (kernel file and the headers it includes) of the
     multiply kernel the timed step launches."""
     heads = [CSRC / "device.h", CSRC / "dma.h"]
+    if precision == "f16x3" and not f16x3_staged:  # hi/lo split in registers from the FP32 tiles
+        return "multiply_f16x3_fused_kernel", [CSRC / "multiply_lowp.hip", *heads]
     if precision != "fp32":
         return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", [CSRC / "multiply_lowp.hip", *heads]
     if leaf == 64 and n % 128 == 0:  # the launch is two kernels: the multiply, then the split-tile fixup
@@ -198,7 +203,8 @@ def main() -> int:
     c = torch.empty_like(a)
     ws = sp.workspace(n, leaf, dev)
     bufs = sp.plan_buffers(n, leaf, dev)
-    split_buf = sp.split_buffer(n, prec, dev) if prec != "fp32" else None
+    split_buf = sp.split_buffer(n, prec, dev) if prec == "bf16" else None
+    header = torch.empty(256, dtype=torch.uint8, device=dev) if prec == "f16x3" else None
 
     # a device-to-device copy of known size, for scaling HBM byte counters
     calib = torch.empty(CALIB_BYTES, dtype=torch.uint8, device=dev)
@@ -210,16 +216,32 @@ def main() -> int:
     # spamm_execute as its two launch steps, so that events on the stream the
     # library launches on (torch's current stream, passed by the binding)
     # bracket the multiply kernel alone.
-    # With reduced-precision products the first stage also writes the split
-    # operands (spamm_prepare_split) and the multiply reads them.
+    # BF16 products: the first stage also writes the split operands
+    # (spamm_prepare_split) and the multiply reads them.  FP16 hi+lo: the first
+    # stage adds the scale exponents (spamm_prepare_scales) and the multiply
+    # splits the FP32 tiles in registers (spamm_execute_f16x3_scheduled).
+    # As spamm_multiply_precision does on the device, FP16 hi+lo takes the
+    # split planes when the plan keeps >= 25 pairs per output tile on average
+    # (decided here once, from the pair count of a first pass).
+    f16x3_staged = False
+    if prec == "f16x3":
+        sp.prepare(a, b, tau, leaf, bufs=bufs, ws=ws)
+        f16x3_staged = int(bufs[2].item()) >= F16X3_STAGED_PAIRS_PER_TILE * (n // leaf) ** 2
+        if f16x3_staged:
+            split_buf = sp.split_buffer(n, prec, dev)
+
     def stage_prepare(t):
         if prec == "fp32":
             return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
+        if prec == "f16x3" and not f16x3_staged:
+            return sp.prepare_scales(a, b, t, leaf, header, bufs=bufs, ws=ws)
         return sp.prepare_split(a, b, t, leaf, prec, split_buf, bufs=bufs, ws=ws)
 
     def stage_multiply(offsets, klist):
         if prec == "fp32":
             sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
+        elif prec == "f16x3" and not f16x3_staged:
+            sp.execute_f16x3(a, b, leaf, header, offsets, klist, c=c, ws=ws)
         else:
             sp.execute_split(split_buf, n, leaf, prec, offsets, klist, c=c, ws=ws, scheduled=True)
 
@@ -250,7 +272,7 @@ def main() -> int:
         pairs = int(bufs[2].item())
         return total / steps, stages, pairs
 
-    kname, ksrc = multiply_kernel(n, leaf, prec)
+    kname, ksrc = multiply_kernel(n, leaf, prec, f16x3_staged)
     workload = workload_name(n, leaf, tau, args.workload, args.alpha, prec)
     log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
     ms_step, (prep_ms, sched_ms, kern_ms), pairs = timed(tau, args.steps, args.warmup)

@@ -186,6 +186,35 @@ spamm_status spamm_execute_split_scheduled(const void* split, int64_t n, int32_t
                                            const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
                                            size_t workspace_bytes, void* stream);
 
+/* The F16X3 scale exponents alone, as spamm_split writes them into the first
+ * 256 bytes of its buffer (int32 exponents of A and B at byte 0, their
+ * largest leaf norms as doubles at byte 8), from the pyramids of A and B.
+ * header: device, 256-byte aligned, header_bytes >= 256.  EINVAL: null
+ * pointer, misalignment, bad size; ENOSPACE: header_bytes < 256;
+ * EUNSUPPORTED: leaf or n outside the reduced-precision shapes. */
+spamm_status spamm_split_scales(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf, void* header,
+                                size_t header_bytes, void* stream);
+
+/* F16X3 products straight from the FP32 inputs, after spamm_schedule on the
+ * same plan and workspace: one kernel stages FP32 tiles of A and B and splits
+ * them into hi and lo in registers with the exponents of `header`
+ * (spamm_split_scales), so C is bitwise the C of spamm_split +
+ * spamm_execute_split_scheduled without the split pass over A and B.  a, b:
+ * device, 16-byte aligned.  Errors as spamm_execute_split_scheduled (EINVAL
+ * also for c overlapping the header). */
+spamm_status spamm_execute_f16x3_scheduled(const float* a, const float* b, int64_t n, int32_t leaf,
+                                           const void* header, const int32_t* offsets, const int32_t* klist,
+                                           float* c, void* workspace, size_t workspace_bytes, void* stream);
+
+/* spamm_prepare followed by spamm_split_scales on the pyramids it leaves in
+ * the workspace (the first stage of the F16X3 path of
+ * spamm_multiply_precision).  Errors as spamm_prepare and spamm_split_scales
+ * (EINVAL also for a header overlapping a or b). */
+spamm_status spamm_prepare_scales(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                  int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs,
+                                  void* header, size_t header_bytes, void* workspace, size_t workspace_bytes,
+                                  void* stream);
+
 /* spamm_prepare followed by spamm_split on the pyramids it leaves in the
  * workspace (the first half of spamm_multiply_precision).  Errors as
  * spamm_prepare and spamm_split. */
@@ -194,9 +223,18 @@ spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, doub
                                  int64_t* pairs, void* split, size_t split_bytes, void* workspace,
                                  size_t workspace_bytes, void* stream);
 
-/* The whole path with reduced-precision products: spamm_prepare_split, then
- * spamm_execute_split.  SPAMM_PREC_FP32 is spamm_multiply (split unused, may be
- * NULL).  Errors as spamm_multiply and spamm_split. */
+/* The whole path with reduced-precision products.  BF16: spamm_prepare_split,
+ * then spamm_execute_split.  F16X3: spamm_prepare_scales into the first 256
+ * bytes of `split`, spamm_schedule, then either the planes and the split
+ * multiply (spamm_split's planes, spamm_execute_split_scheduled) or the
+ * in-register split (spamm_execute_f16x3_scheduled), picked on the device from
+ * the plan's pair count: the planes when it keeps at least 25 pairs per output
+ * tile on average.  With split_bytes below spamm_split_bytes (at least 256),
+ * always in registers and the planes are not written.  Either way C is
+ * bitwise the C of the split path.  SPAMM_PREC_FP32 is spamm_multiply (split unused, may be NULL).
+ * Errors as spamm_multiply and spamm_split (F16X3: EINVAL for a header that
+ * is null, not 256-byte aligned or overlapping a, b or c; ENOSPACE below 256
+ * bytes). */
 spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
                                       int32_t precision, float* c, int64_t* pairs, void* split, size_t split_bytes,
                                       void* workspace, size_t workspace_bytes, void* stream);

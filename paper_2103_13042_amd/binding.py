@@ -56,6 +56,9 @@ _SIGS = {
     "spamm_split": (_st, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "spamm_execute_split": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_execute_split_scheduled": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_split_scales": (_st, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "spamm_prepare_scales": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
+    "spamm_execute_f16x3_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare_split": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_multiply_precision": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_batch_workspace_bytes": (_sz, [_i32, _vp, _vp]),
@@ -496,6 +499,47 @@ def execute_split(split_buf, n: int, leaf: int, precision, offsets, klist, *, c=
     fn = _lib.spamm_execute_split_scheduled if scheduled else _lib.spamm_execute_split
     _check(fn(_ptr(split_buf), n, leaf, _prec(precision), _ptr(offsets), _ptr(klist), _ptr(c), _ptr(ws), ws.numel(),
               _stream(dev)), "spamm_execute_split")
+    return c
+
+
+def split_scales(pyr_a, pyr_b, n: int, leaf: int, header=None) -> torch.Tensor:
+    """The f16x3 scale exponents into a 256-byte header (spamm_split_scales)."""
+    dev = pyr_a.device
+    header = torch.empty(256, dtype=torch.uint8, device=dev) if header is None else header
+    _check(_lib.spamm_split_scales(_ptr(pyr_a), _ptr(pyr_b), n, leaf, _ptr(header), header.numel(), _stream(dev)),
+           "spamm_split_scales")
+    return header
+
+
+def prepare_scales(a, b, tau: float, leaf: int, header, *, bufs=None, ws=None):
+    """spamm_prepare + spamm_split_scales on the workspace pyramids: (offsets, klist, pairs)."""
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    dev = a.device
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    offsets, klist, pairs = plan_buffers(n, leaf, dev) if bufs is None else bufs
+    _check(_lib.spamm_prepare_scales(_ptr(a), _ptr(b), n, float(tau), leaf, _ptr(offsets), _ptr(klist), klist.numel(),
+                                     _ptr(pairs), _ptr(header), header.numel(), _ptr(ws), ws.numel(), _stream(dev)),
+           "spamm_prepare_scales")
+    return offsets, klist, pairs
+
+
+def execute_f16x3(a, b, leaf: int, header, offsets, klist, *, c=None, ws=None) -> torch.Tensor:
+    """f16x3 products straight from the FP32 inputs after schedule()
+    (spamm_execute_f16x3_scheduled)."""
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    dev = a.device
+    _check_plan(offsets, klist, n, leaf, dev)
+    c = torch.empty_like(a) if c is None else c
+    if _square_f32(c, "c") != n:
+        raise ValueError("c must be n x n")
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    _check(_lib.spamm_execute_f16x3_scheduled(_ptr(a), _ptr(b), n, leaf, _ptr(header), _ptr(offsets), _ptr(klist),
+                                              _ptr(c), _ptr(ws), ws.numel(), _stream(dev)),
+           "spamm_execute_f16x3_scheduled")
     return c
 
 

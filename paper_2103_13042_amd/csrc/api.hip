@@ -216,6 +216,14 @@ spamm_status enqueue_execute(const Geom& g, const float* a, const float* b, cons
 }
 
 namespace {
+constexpr size_t kSplitHeaderBytes = 256;  // scale exponents and largest leaf norms
+// F16X3 whole path: split A and B once when the plan keeps at least this many
+// pairs per output tile on average, else split in registers.  The in-register
+// split costs about 0.6 ns per kept pair more in the multiply (measured on the
+// dense N = 16384 ReLU-like pair, where it is VALU-bound), the split pass
+// about 15 ns per output tile (it reads and writes A and B: 1 ms at
+// N = 16384, 65,536 tiles), so they break even near 25 pairs per tile.
+constexpr int64_t kF16x3StagedPairsPerTile = 25;
 size_t plane_bytes(int64_t n) { return (size_t(n) * size_t(n) * 2 + 255) / 256 * 256; }
 int split_planes(int32_t precision) { return precision == spamm::kPrecF16x3 ? 4 : 2; }
 
@@ -224,7 +232,7 @@ spamm::SplitLayout split_layout(void* split, int64_t n, int32_t precision) {
     const size_t pb = plane_bytes(n);
     spamm::SplitLayout L{};
     L.exps = reinterpret_cast<int32_t*>(base);
-    char* p = base + 256;
+    char* p = base + kSplitHeaderBytes;
     auto next = [&]() {
         uint16_t* q = reinterpret_cast<uint16_t*>(p);
         p += pb;
@@ -409,7 +417,7 @@ spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double ta
 
 size_t spamm_split_bytes(int64_t n, int32_t precision) {
     if (n <= 0 || (precision != spamm::kPrecBf16 && precision != spamm::kPrecF16x3)) return 0;
-    return 256 + size_t(split_planes(precision)) * plane_bytes(n);
+    return kSplitHeaderBytes + size_t(split_planes(precision)) * plane_bytes(n);
 }
 
 spamm_status spamm_split(const float* a, const float* b, int64_t n, int32_t leaf, int32_t precision,
@@ -449,7 +457,7 @@ spamm_status spamm_execute_split_scheduled(const void* split, int64_t n, int32_t
     const Layout L = make_layout(g);
     return hip_check(spamm::launch_lowp_multiply(split_layout(const_cast<void*>(split), n, precision), c, n, g.bdim,
                                                  precision, at<uint32_t>(workspace, L.mitems),
-                                                 at<int32_t>(workspace, L.mprefix), device_cus(),
+                                                 at<int32_t>(workspace, L.mprefix), device_cus(), spamm::PairGate{},
                                                  static_cast<hipStream_t>(stream)),
                      "reduced-precision multiply kernel");
 }
@@ -461,6 +469,63 @@ spamm_status spamm_execute_split(const void* split, int64_t n, int32_t leaf, int
     if (st != SPAMM_OK) return st;
     return spamm_execute_split_scheduled(split, n, leaf, precision, offsets, klist, c, workspace, workspace_bytes,
                                          stream);
+}
+
+spamm_status spamm_split_scales(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf, void* header,
+                                size_t header_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!pyr_a || !pyr_b || !header) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_lowp(g, spamm::kPrecF16x3);
+    if (st != SPAMM_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(header) & 255u) != 0) return fail(SPAMM_EINVAL, "header must be 256-byte aligned");
+    if (header_bytes < kSplitHeaderBytes)
+        return fail(SPAMM_ENOSPACE, "header of %zu bytes, %zu needed", header_bytes, kSplitHeaderBytes);
+    return hip_check(spamm::launch_split_scales(g.bdim, g.lv, pyr_a, pyr_b, static_cast<int32_t*>(header),
+                                                static_cast<hipStream_t>(stream)),
+                     "scale kernels");
+}
+
+spamm_status spamm_execute_f16x3_scheduled(const float* a, const float* b, int64_t n, int32_t leaf,
+                                           const void* header, const int32_t* offsets, const int32_t* klist,
+                                           float* c, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!header || !offsets || !klist) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_mul_args(g, a, b, c);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_lowp(g, spamm::kPrecF16x3)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
+    if (overlaps(c, sizeof(float) * size_t(n) * size_t(n), header, kSplitHeaderBytes))
+        return fail(SPAMM_EINVAL, "c overlaps the header");
+    const Layout L = make_layout(g);
+    return hip_check(spamm::launch_f16x3_fused_multiply(a, b, static_cast<const int32_t*>(header), c, n, g.bdim,
+                                                        at<uint32_t>(workspace, L.mitems),
+                                                        at<int32_t>(workspace, L.mprefix), device_cus(),
+                                                        spamm::PairGate{}, static_cast<hipStream_t>(stream)),
+                     "fused f16x3 multiply kernel");
+}
+
+spamm_status spamm_prepare_scales(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                  int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs,
+                                  void* header, size_t header_bytes, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_lowp(g, spamm::kPrecF16x3);
+    if (st != SPAMM_OK) return st;
+    const size_t mbytes = sizeof(float) * size_t(n) * size_t(n);
+    if (header && (overlaps(header, kSplitHeaderBytes, a, mbytes) || overlaps(header, kSplitHeaderBytes, b, mbytes)))
+        return fail(SPAMM_EINVAL, "header overlaps a or b");
+    st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, klist_capacity, pairs, workspace, workspace_bytes, stream);
+    if (st != SPAMM_OK) return st;
+    const Layout L = make_layout(g);
+    return spamm_split_scales(at<double>(workspace, L.pyr[0]), at<double>(workspace, L.pyr[1]), n, leaf, header,
+                              header_bytes, stream);
 }
 
 spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
@@ -496,6 +561,45 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
     int32_t* offsets = at<int32_t>(workspace, L.offsets);
     int32_t* klist = at<int32_t>(workspace, L.klist);
     int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
+    if (precision == spamm::kPrecF16x3) {
+        // With room for the planes the device picks, from the plan's pair
+        // count, between splitting A and B once and multiplying the planes
+        // (many pairs: each tile feeds many products) and splitting the FP32
+        // tiles in registers inside the multiply (few pairs: the split pass
+        // would cost more than the conversions).  With only the header, always
+        // in registers.  Both give bitwise the same C.
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
+        const bool planes = split_bytes >= spamm_split_bytes(n, precision);
+        if (planes) {
+            const size_t sb = spamm_split_bytes(n, precision), mbytes = sizeof(float) * size_t(n) * size_t(n);
+            if (!split || overlaps(split, sb, a, mbytes) || overlaps(split, sb, b, mbytes) ||
+                overlaps(split, sb, c, mbytes))
+                return fail(SPAMM_EINVAL, "split buffer null or overlapping a, b or c");
+        }
+        st = spamm_prepare_scales(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, split, split_bytes,
+                                  workspace, workspace_bytes, stream);
+        if (st != SPAMM_OK) return st;
+        spamm::PairGate staged{np, kF16x3StagedPairsPerTile * g.bdim * g.bdim, 1}, fused{};
+        const spamm::SplitLayout SL = split_layout(split, n, precision);
+        if (planes) {
+            fused = staged;
+            fused.when_at_least = 0;
+            if ((st = hip_check(spamm::launch_split_planes(a, b, n, precision, SL, staged, s), "split kernels")) !=
+                SPAMM_OK)
+                return st;
+        }
+        if ((st = enqueue_schedule(g, offsets, klist, workspace, s)) != SPAMM_OK) return st;
+        if (planes &&
+            (st = hip_check(spamm::launch_lowp_multiply(SL, c, n, g.bdim, precision, at<uint32_t>(workspace, L.mitems),
+                                                        at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),
+                            "reduced-precision multiply kernel")) != SPAMM_OK)
+            return st;
+        return hip_check(spamm::launch_f16x3_fused_multiply(a, b, SL.exps, c, n, g.bdim,
+                                                            at<uint32_t>(workspace, L.mitems),
+                                                            at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
+                         "fused f16x3 multiply kernel");
+    }
     st = spamm_prepare_split(a, b, n, tau, leaf, precision, offsets, klist, g.ntiles * g.bdim, np, split,
                              split_bytes, workspace, workspace_bytes, stream);
     if (st != SPAMM_OK) return st;

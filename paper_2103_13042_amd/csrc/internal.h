@@ -143,10 +143,32 @@ struct SplitLayout {
     uint16_t *a_hi, *a_lo, *bt_hi, *bt_lo;
 };
 
+// A launch that runs only when the pair count the plan left on the device is
+// at least (when_at_least = 1) or below (0) a threshold; pairs == nullptr:
+// always.  Lets one stream hold both forms of a step and the device pick.
+struct PairGate {
+    const int64_t* pairs = nullptr;
+    int64_t threshold = 0;
+    int when_at_least = 1;
+};
+
 hipError_t launch_split(const float* a, const float* b, int64_t n, int64_t bdim, int lv, const double* pyr_a,
                         const double* pyr_b, int precision, const SplitLayout& L, hipStream_t s);
+// The planes alone, after the exponents (launch_split_scales) are in L.exps.
+hipError_t launch_split_planes(const float* a, const float* b, int64_t n, int precision, const SplitLayout& L,
+                               const PairGate& gate, hipStream_t s);
+// The f16x3 scale exponents alone (int32 exps at header[0..1], the two
+// largest leaf norms at header + 8 bytes).
+hipError_t launch_split_scales(int64_t bdim, int lv, const double* pyr_a, const double* pyr_b, int32_t* header,
+                               hipStream_t s);
+// f16x3 products straight from the FP32 inputs (the split done in registers),
+// bitwise the same C as launch_split + launch_lowp_multiply.
+hipError_t launch_f16x3_fused_multiply(const float* a, const float* b, const int32_t* exps, float* c, int64_t n,
+                                       int64_t bdim, const uint32_t* items, const int32_t* uprefix, int num_cus,
+                                       const PairGate& gate, hipStream_t s);
 hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64_t bdim, int precision,
-                                const uint32_t* items, const int32_t* uprefix, int num_cus, hipStream_t s);
+                                const uint32_t* items, const int32_t* uprefix, int num_cus, const PairGate& gate,
+                                hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Batched products (kernels.hip): one descriptor per product in device memory.

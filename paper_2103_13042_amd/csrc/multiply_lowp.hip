@@ -33,13 +33,17 @@ struct LowpGeom {
 };
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 template <int MODE>
 __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
     const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al, const uint16_t* __restrict__ Bh,
     const uint16_t* __restrict__ Bl, const int32_t* __restrict__ exps, float* __restrict__ C, int64_t n,
-    int64_t bdim, int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix) {
+    int64_t bdim, int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix, PairGate gate) {
+    if (!gate_open(gate)) return;
     using G = LowpGeom<MODE>;
     constexpr int LEAF = 64, S = G::S;
     __shared__ __attribute__((aligned(1024))) char lds[S * G::STAGE];
@@ -197,8 +201,210 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
     __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
 }
 
+// ---------------------------------------------------------------------------
+// FP16 hi+lo products straight from the FP32 inputs: the copies, LDS stages
+// and swizzles of the FP32 DMA kernel (multiply_macro.hip: A rows of 64
+// floats, chunk c of row r at c ^ (r & 15); B rows of 128 floats, chunk p of
+// row r at p ^ (8 ((r >> 5) & 1))), and at the operand reads the split of
+// split.hip (y = s x, hi = fp16(y), lo = fp16(y - hi), nearest-even) in
+// registers, then the MFMA sequence of multiply_lowp_kernel<kPrecF16x3>: per
+// k-step s4 = 0..3 (k = 16 s4 + 8 (lane >> 5) + 0..7) hi*hi, hi*lo, lo*hi.  The
+// same operand values, the same products in the same order and the same
+// workgroup partition (whole macro tiles) as the split path, so C is
+// bitwise the same, without the split pass's read and write of A and B.
+__global__ __launch_bounds__(kDmaThreads, 1) void multiply_f16x3_fused_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, const int32_t* __restrict__ exps, float* __restrict__ C,
+    int64_t n, int64_t bdim, int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix,
+    PairGate gate) {
+    if (!gate_open(gate)) return;
+    constexpr int LEAF = 64, KC = 64, S = 2;
+    constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;
+    constexpr int STAGE_BYTES = ABYTES + BBYTES;
+    constexpr int COPIES = 2 * KC / 32;  // per wave per item
+    static_assert(S * STAGE_BYTES <= 160 * 1024, "LDS budget");
+    __shared__ __attribute__((aligned(1024))) char lds[S * STAGE_BYTES];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
+              qc = (wave >> 2) & 1;
+    const int ir = lane & 31, g = lane >> 5;
+
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t nm = mb * mb;
+    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
+    auto start_of = [&](int64_t gg) {
+        const int64_t target = gg * total;
+        int64_t lo = 0, hi = nm;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    };
+    const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
+    if (m_begin >= m_end) return;
+    const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]);
+    const float sa_scale = ldexpf(1.0f, exps[0]), sb_scale = ldexpf(1.0f, exps[1]);
+    const float inv = ldexpf(1.0f, -(exps[0] + exps[1]));
+
+    const uint32_t* ip = items + uprefix[m_begin];
+    int64_t pp = 0;
+    uint32_t last = 0;
+    auto produce = [&]() -> uint32_t {
+        if (pp < nitems) last = ip[pp];
+        ++pp;
+        return last;
+    };
+
+    f16v acc;
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    };
+    auto store_macro = [&](int64_t m) {  // exactly kDmaStores stores per wave
+        const int64_t ti = 2 * (m / mb) + wa, tj = 2 * (m - (m / mb) * mb) + wb;
+        float* dst = C + (ti * LEAF + qr * 32 + 4 * g) * n + tj * LEAF + qc * 32 + ir;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[(8 * (r >> 2) + (r & 3)) * n] = acc[r] * inv;
+    };
+    // copies of item pi into stage st: 2 A and 2 B instructions of 1 KiB per wave
+    constexpr int ACH = KC / 4;  // 16-byte chunks per A row
+    auto copy_item = [&](uint32_t pi, int st) {
+        const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
+        char* sbase = lds + st * STAGE_BYTES;
+#pragma unroll
+        for (int j = 0; j < KC / 32; ++j) {  // A: 4 rows of 16 chunks per instruction
+            const int blk = wave * (KC / 32) + j;
+            const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
+            const int c = p ^ (r & 15);
+            const float* src = A + (2 * I * LEAF + r) * n + kt * LEAF + 4 * c;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sbase + blk * 1024), 16, 0,
+                                             0);
+        }
+#pragma unroll
+        for (int j = 0; j < KC / 32; ++j) {  // B: 2 rows of 32 chunks per instruction
+            const int blk = wave * (KC / 32) + j;
+            const int r = blk * 2 + (lane >> 5), p = lane & 31;
+            const int c = p ^ (8 * ((r >> 5) & 1));
+            const float* src = B + (kt * LEAF + r) * n + 2 * J * LEAF + 4 * c;
+            __builtin_amdgcn_global_load_lds(src,
+                                             (__attribute__((address_space(3))) void*)(sbase + ABYTES + blk * 1024),
+                                             16, 0, 0);
+        }
+    };
+    // two elements at a time, as split.hip's Conv<kPrecF16x3>: y = s x (exact),
+    // hi = fp16(y), lo = fp16(y - hi) (y - hi exact), nearest-even; then four
+    // pairs make one 8-half MFMA operand
+    auto split2 = [](float x0, float x1, float s, h2& hi, h2& lo) {
+        const f2 y = {x0 * s, x1 * s};
+        hi = __builtin_convertvector(y, h2);
+        lo = __builtin_convertvector(y - __builtin_convertvector(hi, f2), h2);
+    };
+    auto cat8 = [](h2 p0, h2 p1, h2 p2, h2 p3) {
+        const h4 q0 = __builtin_shufflevector(p0, p1, 0, 1, 2, 3), q1 = __builtin_shufflevector(p2, p3, 0, 1, 2, 3);
+        return h8(__builtin_shufflevector(q0, q1, 0, 1, 2, 3, 4, 5, 6, 7));
+    };
+    auto compute = [&](int st) {
+        const char* sa = lds + st * STAGE_BYTES;
+        const char* sb = sa + ABYTES;
+        const int ra = wa * 64 + qr * 32 + ir;
+        const int cc = wb * 64 + qc * 32 + ir;
+        // k-step s4 covers k = 16 s4 + 8 g .. + 7 of this lane's A row and B column
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int q0 = 4 * s4 + 2 * g;
+            const f4 a0 = *reinterpret_cast<const f4*>(sa + ra * (KC * 4) + ((q0 ^ (ra & 15)) * 16));
+            const f4 a1 = *reinterpret_cast<const f4*>(sa + ra * (KC * 4) + (((q0 + 1) ^ (ra & 15)) * 16));
+            const char* bcol = sb + ((cc >> 2) ^ (8 * (s4 >> 1))) * 16 + (cc & 3) * 4;
+            float bv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                bv[i] = *reinterpret_cast<const float*>(bcol + (16 * s4 + 8 * g + i) * (2 * LEAF * 4));
+            h2 ph[4], pl[4];
+            split2(a0[0], a0[1], sa_scale, ph[0], pl[0]);
+            split2(a0[2], a0[3], sa_scale, ph[1], pl[1]);
+            split2(a1[0], a1[1], sa_scale, ph[2], pl[2]);
+            split2(a1[2], a1[3], sa_scale, ph[3], pl[3]);
+            const h8 ah = cat8(ph[0], ph[1], ph[2], ph[3]), al = cat8(pl[0], pl[1], pl[2], pl[3]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) split2(bv[2 * i], bv[2 * i + 1], sb_scale, ph[i], pl[i]);
+            const h8 bh = cat8(ph[0], ph[1], ph[2], ph[3]), bl = cat8(pl[0], pl[1], pl[2], pl[3]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    uint32_t f[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) f[i] = produce();
+#pragma unroll
+    for (int i = 0; i < S - 1; ++i) copy_item(f[i], i);
+    int64_t out_m = m_begin;
+    int ns[S];  // macro tiles stored in the last S-1 steps (ns[0]: this step)
+#pragma unroll
+    for (int i = 0; i < S; ++i) ns[i] = 0;
+    zero_acc();
+    for (int64_t it = 0; it < nitems; ++it) {
+        const uint32_t pi = f[0];
+        const int64_t m_it = int64_t(pi >> 23) * mb + ((pi >> 14) & 511);
+#pragma unroll
+        for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
+        ns[0] = 0;
+        while (out_m < m_it) {
+            store_macro(out_m);
+            zero_acc();
+            ++out_m;
+            ++ns[0];
+        }
+        int stores = 0;
+#pragma unroll
+        for (int i = 0; i < S - 1; ++i) stores += ns[i];
+        asm volatile("" ::: "memory");
+        wait_copies<(S - 2) * COPIES>(stores);
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        copy_item(f[S - 1], int((it + S - 1) % S));  // item it+S-1 -> the stage item it-1 used
+        if ((pi >> tile) & 1) compute(int(it % S));
+#pragma unroll
+        for (int i = 0; i < S - 1; ++i) f[i] = f[i + 1];
+        f[S - 1] = produce();
+    }
+    int64_t m_last = out_m;
+    while (m_last < m_end) {
+        store_macro(m_last);
+        zero_acc();
+        ++m_last;
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
+}
+
+hipError_t launch_f16x3_fused_multiply(const float* a, const float* b, const int32_t* exps, float* c, int64_t n,
+                                       int64_t bdim, const uint32_t* items, const int32_t* uprefix, int num_cus,
+                                       const PairGate& gate, hipStream_t s) {
+    const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
+    const int64_t cap = ((nm + 7) / 8) * 8;
+    int64_t groups = int64_t(num_cus);
+    if (groups > cap) groups = cap;
+    groups = ((groups + 7) / 8) * 8;
+    static int scratch_state = 0;
+    const hipError_t ce = check_no_scratch(multiply_f16x3_fused_kernel, &scratch_state);
+    if (ce != hipSuccess) return ce;
+    multiply_f16x3_fused_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, exps, c, n, bdim, mb, items, uprefix,
+                                                                        gate);
+    return hipGetLastError();
+}
+
 hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64_t bdim, int precision,
-                                const uint32_t* items, const int32_t* uprefix, int num_cus, hipStream_t s) {
+                                const uint32_t* items, const int32_t* uprefix, int num_cus, const PairGate& gate,
+                                hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int64_t cap = ((nm + 7) / 8) * 8;
     int64_t groups = int64_t(num_cus);
@@ -209,12 +415,12 @@ hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64
         const hipError_t ce = check_no_scratch(multiply_lowp_kernel<kPrecBf16>, &scratch_bf16);
         if (ce != hipSuccess) return ce;
         multiply_lowp_kernel<kPrecBf16><<<unsigned(groups), kDmaThreads, 0, s>>>(
-            L.a_hi, L.a_lo, L.bt_hi, L.bt_lo, L.exps, c, n, bdim, mb, items, uprefix);
+            L.a_hi, L.a_lo, L.bt_hi, L.bt_lo, L.exps, c, n, bdim, mb, items, uprefix, gate);
     } else {
         const hipError_t ce = check_no_scratch(multiply_lowp_kernel<kPrecF16x3>, &scratch_f16);
         if (ce != hipSuccess) return ce;
         multiply_lowp_kernel<kPrecF16x3><<<unsigned(groups), kDmaThreads, 0, s>>>(
-            L.a_hi, L.a_lo, L.bt_hi, L.bt_lo, L.exps, c, n, bdim, mb, items, uprefix);
+            L.a_hi, L.a_lo, L.bt_hi, L.bt_lo, L.exps, c, n, bdim, mb, items, uprefix, gate);
     }
     return hipGetLastError();
 }

@@ -78,7 +78,8 @@ struct Conv<kPrecF16x3> {
 template <int MODE>
 __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict__ x, int64_t count,
                                                          const int32_t* __restrict__ exps, uint16_t* __restrict__ hi,
-                                                         uint16_t* __restrict__ lo) {
+                                                         uint16_t* __restrict__ lo, PairGate gate) {
+    if (!gate_open(gate)) return;
     const float s = MODE == kPrecF16x3 ? ldexpf(1.0f, exps[0]) : 1.0f;
     const int64_t n4 = count / 4;
     const f4* x4 = reinterpret_cast<const f4*>(x);
@@ -101,7 +102,9 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict
 template <int MODE>
 __global__ __launch_bounds__(256) void split_transpose_kernel(const float* __restrict__ x, int64_t n,
                                                               const int32_t* __restrict__ exps,
-                                                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+                                                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                                                              PairGate gate) {
+    if (!gate_open(gate)) return;
     __shared__ float t[64][65];
     const float s = MODE == kPrecF16x3 ? ldexpf(1.0f, exps[1]) : 1.0f;
     const int64_t r0 = int64_t(blockIdx.y) * 64, c0 = int64_t(blockIdx.x) * 64;
@@ -141,28 +144,38 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float* __res
     }
 }
 
-hipError_t launch_split(const float* a, const float* b, int64_t n, int64_t bdim, int lv, const double* pyr_a,
-                        const double* pyr_b, int precision, const SplitLayout& L, hipStream_t s) {
+hipError_t launch_split_scales(int64_t bdim, int lv, const double* pyr_a, const double* pyr_b, int32_t* header,
+                               hipStream_t s) {
     // the header holds exps[2] (bytes 0..7) and the two maxima (bytes 8..23)
-    unsigned long long* mx = reinterpret_cast<unsigned long long*>(L.exps + 2);
+    unsigned long long* mx = reinterpret_cast<unsigned long long*>(header + 2);
     split_scale_init_kernel<<<1, 64, 0, s>>>(mx);
     const int64_t tiles = bdim * bdim;
     const unsigned blocks = unsigned(tiles < 64 * 256 ? (tiles + 255) / 256 : 64);
     split_max_kernel<<<dim3{blocks, 2u, 1u}, 256, 0, s>>>(pyr_a, pyr_b, bdim, lv, mx);
-    split_scale_kernel<<<1, 64, 0, s>>>(mx, L.exps);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    split_scale_kernel<<<1, 64, 0, s>>>(mx, header);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_planes(const float* a, const float* b, int64_t n, int precision, const SplitLayout& L,
+                               const PairGate& gate, hipStream_t s) {
     const int64_t n4 = n * n / 4;
     const unsigned rows_grid = unsigned(n4 < 2048 * 256 ? (n4 + 255) / 256 : 2048);
     const dim3 tgrid{unsigned(n / 64), unsigned(n / 64), 1u};
     if (precision == kPrecBf16) {
-        split_rows_kernel<kPrecBf16><<<rows_grid, 256, 0, s>>>(a, n * n, L.exps, L.a_hi, nullptr);
-        split_transpose_kernel<kPrecBf16><<<tgrid, 256, 0, s>>>(b, n, L.exps, L.bt_hi, nullptr);
+        split_rows_kernel<kPrecBf16><<<rows_grid, 256, 0, s>>>(a, n * n, L.exps, L.a_hi, nullptr, gate);
+        split_transpose_kernel<kPrecBf16><<<tgrid, 256, 0, s>>>(b, n, L.exps, L.bt_hi, nullptr, gate);
     } else {
-        split_rows_kernel<kPrecF16x3><<<rows_grid, 256, 0, s>>>(a, n * n, L.exps, L.a_hi, L.a_lo);
-        split_transpose_kernel<kPrecF16x3><<<tgrid, 256, 0, s>>>(b, n, L.exps, L.bt_hi, L.bt_lo);
+        split_rows_kernel<kPrecF16x3><<<rows_grid, 256, 0, s>>>(a, n * n, L.exps, L.a_hi, L.a_lo, gate);
+        split_transpose_kernel<kPrecF16x3><<<tgrid, 256, 0, s>>>(b, n, L.exps, L.bt_hi, L.bt_lo, gate);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_split(const float* a, const float* b, int64_t n, int64_t bdim, int lv, const double* pyr_a,
+                        const double* pyr_b, int precision, const SplitLayout& L, hipStream_t s) {
+    hipError_t e = launch_split_scales(bdim, lv, pyr_a, pyr_b, L.exps, s);
+    if (e != hipSuccess) return e;
+    return launch_split_planes(a, b, n, precision, L, PairGate{}, s);
 }
 
 }  // namespace spamm

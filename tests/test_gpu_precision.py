@@ -105,6 +105,44 @@ def test_staged_split_path_equals_fused(precision):
     sp.schedule(offsets, klist, n, leaf, ws=ws)
     c2 = sp.execute_split(buf, n, leaf, precision, offsets, klist, ws=ws, scheduled=True)
     assert torch.equal(c_fused, c1) and torch.equal(c1, c2)
+    if precision == "f16x3":  # the stages of the in-register split: bitwise the same C
+        header = torch.zeros(256, dtype=torch.uint8, device=DEV)
+        o3, k3, _ = sp.prepare_scales(ga, gb, tau, leaf, header, ws=ws)
+        assert torch.equal(header[:8], buf[:8])
+        sp.schedule(o3, k3, n, leaf, ws=ws)
+        assert torch.equal(sp.execute_f16x3(ga, gb, leaf, header, o3, k3, ws=ws), c1)
+
+
+def test_f16x3_whole_path_needs_only_the_split_header():
+    n, leaf, tau = 512, 64, 1e-6
+    a, b = gpu(inputs.exp_decay(n, 0.05, 7)), gpu(inputs.exp_decay(n, 0.05, 8))
+    c_full, p_full = sp.multiply_precision(a, b, tau, leaf, "f16x3", split_buf=sp.split_buffer(n, "f16x3", DEV))
+    header = torch.zeros(256, dtype=torch.uint8, device=DEV)
+    c_head, p_head = sp.multiply_precision(a, b, tau, leaf, "f16x3", split_buf=header)
+    assert p_full == p_head and torch.equal(c_full, c_head)
+    ea, eb = (pr.f16_scale_exponent(pr.max_leaf_norm(x.cpu().numpy(), leaf)) for x in (a, b))
+    assert header[:8].view(torch.int32).cpu().tolist() == [ea, eb]
+    with pytest.raises(sp.SpammError) as e:
+        sp.multiply_precision(a, b, tau, leaf, "f16x3", split_buf=torch.zeros(255, dtype=torch.uint8, device=DEV))
+    assert e.value.status == 2
+    big = torch.zeros(1024, dtype=torch.uint8, device=DEV)
+    with pytest.raises(sp.SpammError) as e:
+        sp.multiply_precision(a, b, tau, leaf, "f16x3", split_buf=big[16:])  # not 256-byte aligned
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-6])
+def test_f16x3_whole_path_picks_either_form_with_the_same_result(tau):
+    # n = 2048, leaf 64: the planes are used at >= 25 pairs per output tile
+    # (tau = 0: 32 per tile), the in-register split below (tau = 1e-6 on this
+    # exponential decay); the header-only call always splits in registers
+    n, leaf = 2048, 64
+    a, b = gpu(inputs.exp_decay(n, 0.02, 21)), gpu(inputs.exp_decay(n, 0.02, 22))
+    c_adapt, p_adapt = sp.multiply_precision(a, b, tau, leaf, "f16x3")
+    c_reg, p_reg = sp.multiply_precision(a, b, tau, leaf, "f16x3",
+                                         split_buf=torch.zeros(256, dtype=torch.uint8, device=DEV))
+    assert p_adapt == p_reg and torch.equal(c_adapt, c_reg)
+    assert (p_adapt >= 25 * (n // leaf) ** 2) == (tau == 0.0)
 
 
 def test_zero_and_tau_above_every_product():
