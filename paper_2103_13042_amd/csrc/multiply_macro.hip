@@ -12,10 +12,11 @@
 // Work units: a persistent grid of G workgroups splits the macro tiles into
 // contiguous row-major ranges of equal cost (kUnionCost per union k plus
 // kMacroWrite per macro tile, from the prefix of union sizes), XCD-aware as in
-// the single-tile kernel.  The schedule step lists, for every macro tile in
-// order, its union k values with the 4-bit membership of the four tiles
-// (packed items); a workgroup streams its contiguous slice of that list with
-// scalar loads, a few items ahead of the one it multiplies.
+// the single-tile kernel; the leaf-64 LDS-DMA kernel below splits at item
+// granularity instead (see its comment).  The schedule step lists, for every
+// macro tile in order, its union k values with the 4-bit membership of the
+// four tiles (packed items); a workgroup streams its contiguous slice of that
+// list with scalar loads, a few items ahead of the one it multiplies.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
