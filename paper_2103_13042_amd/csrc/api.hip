@@ -73,11 +73,19 @@ Layout make_layout(const Geom& g) {
     L.mcount = take(sizeof(int32_t) * nm);
     L.mprefix = take(sizeof(int32_t) * (nm + 1));
     L.mitems = take(sizeof(uint32_t) * nm * size_t(g.bdim));
+    // leaf 128 on the LDS-DMA kernel: two items per kept pair, their prefix
+    const bool l128 = g.leaf == 128 && g.n % 128 == 0 && g.bdim <= spamm::kLeaf128MaxBdim;
+    L.leaf128_dma = l128;
+    L.items128 = take(l128 ? sizeof(uint32_t) * 2 * size_t(g.ntiles) * size_t(g.bdim) : 0);
+    L.uprefix128 = take(l128 ? sizeof(int32_t) * size_t(g.ntiles + 1) : 0);
     L.bounds = take(sizeof(int64_t) * 4 * spamm::kSplitMaxGroups);
-    // partial sums of shared macro tiles: the leaf-64 LDS-DMA kernel only,
-    // two slots per workgroup (at most one workgroup per 2x2 macro tile)
-    const bool dma = g.leaf == 64 && g.n % 128 == 0;
-    const size_t groups = nm < size_t(spamm::kSplitMaxGroups) ? (nm + 7) / 8 * 8 : size_t(spamm::kSplitMaxGroups);
+    // partial sums of shared macro tiles (LDS-DMA kernel: leaf 64 or 128, N a
+    // multiple of 128), two slots per workgroup, at most one workgroup per
+    // macro tile
+    const bool dma = (g.leaf == 64 && g.n % 128 == 0) || l128;
+    const size_t macros = l128 ? size_t(g.ntiles) : nm;
+    const size_t groups =
+        macros < size_t(spamm::kSplitMaxGroups) ? (macros + 7) / 8 * 8 : size_t(spamm::kSplitMaxGroups);
     L.fix_slot_bytes = dma ? sizeof(float) * groups * 2 * spamm::kSplitSlotFloats : 0;
     L.fix_slots = take(L.fix_slot_bytes);
     L.pairs = take(sizeof(int64_t));
@@ -189,8 +197,14 @@ spamm::MacroSchedule macro_schedule(const Layout& L, void* ws) {
 }
 
 spamm_status enqueue_schedule(const Geom& g, const int32_t* offsets, const int32_t* klist, void* ws, hipStream_t s) {
-    if (g.leaf != 32 && g.leaf != 64) return SPAMM_OK;  // the single-tile kernel reads the plan directly
     const Layout L = make_layout(g);
+    if (g.leaf == 128) {
+        if (!L.leaf128_dma) return SPAMM_OK;  // the single-tile kernel reads the plan directly
+        return hip_check(spamm::launch_leaf128_schedule(offsets, klist, g.bdim, at<int32_t>(ws, L.uprefix128),
+                                                        at<uint32_t>(ws, L.items128), s),
+                         "leaf-128 schedule kernel");
+    }
+    if (g.leaf != 32 && g.leaf != 64) return SPAMM_OK;
     return hip_check(spamm::launch_macro_schedule(offsets, klist, g.bdim, macro_schedule(L, ws), s),
                      "macro schedule kernels");
 }
@@ -199,6 +213,11 @@ spamm_status enqueue_multiply(const Geom& g, const float* a, const float* b, con
                               const int32_t* klist, float* c, void* ws, hipStream_t s) {
     const bool vec = (g.n % 4) == 0 && aligned16(a) && aligned16(b);
     const Layout L = make_layout(g);
+    if (L.leaf128_dma && vec)
+        return hip_check(spamm::launch_leaf128_multiply(a, b, c, g.n, g.bdim, at<int32_t>(ws, L.uprefix128),
+                                                        at<uint32_t>(ws, L.items128), at<int64_t>(ws, L.bounds),
+                                                        at<float>(ws, L.fix_slots), device_cus(), s),
+                         "leaf-128 multiply kernels");
     if (g.leaf == 32 || g.leaf == 64)
         return hip_check(spamm::launch_macro_multiply(a, b, c, g.n, g.leaf, g.bdim, offsets, macro_schedule(L, ws),
                                                       vec, device_cus(), s),

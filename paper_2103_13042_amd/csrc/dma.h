@@ -77,11 +77,14 @@ static hipError_t check_no_scratch(K kernel, int* state) {
 // kStoreCost per tile + kItemCost per union k (uprefix) + kKeptCost per kept
 // pair, the pairs of the tiles before m read off the plan's offsets (all tile
 // rows above the macro row, and the first 2J tiles of its two tile rows).
+// offsets == nullptr: every item feeds all four quarters (leaf-128 tiles).
 __device__ inline int64_t macro_cost_before(int64_t m, int64_t mb, const int32_t* __restrict__ uprefix,
                                             const int32_t* __restrict__ offsets) {
     const int64_t bdim = 2 * mb;
     int64_t kept;
-    if (m >= mb * mb) {
+    if (offsets == nullptr) {
+        kept = 4 * int64_t(uprefix[m]);
+    } else if (m >= mb * mb) {
         kept = offsets[bdim * bdim];
     } else {
         const int64_t I = m / mb, J = m - (m / mb) * mb, r0 = 2 * I * bdim;

@@ -29,7 +29,8 @@ bool make_geom(int64_t n, int32_t leaf, Geom* g);
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
     size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix,
-        mitems, bounds, fix_slots, fix_slot_bytes, pairs, scalars, partials, total;
+        mitems, items128, uprefix128, bounds, fix_slots, fix_slot_bytes, pairs, scalars, partials, total;
+    bool leaf128_dma;  // leaf 128 runs on the LDS-DMA kernel (items128, uprefix128 in use)
 };
 
 Layout make_layout(const Geom& g);

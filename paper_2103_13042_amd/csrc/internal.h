@@ -81,6 +81,16 @@ hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, i
 hipError_t launch_macro_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
                                  const int32_t* offsets, const MacroSchedule& ms, bool vec, int num_cus,
                                  hipStream_t s);
+// Leaf 128 with N a multiple of 128 (bdim <= kLeaf128MaxBdim) on the LDS-DMA
+// kernel: two items per kept pair (uprefix [bdim*bdim + 1], items
+// [2 * pairs]), then the multiply and fixup kernels with one macro tile per
+// output tile.
+constexpr int64_t kLeaf128MaxBdim = 512;  // item fields: tile index < 512, k half < 1024
+hipError_t launch_leaf128_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, int32_t* uprefix,
+                                   uint32_t* items, hipStream_t s);
+hipError_t launch_leaf128_multiply(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                                   const int32_t* uprefix, const uint32_t* items, int64_t* bounds, float* fix_slots,
+                                   int num_cus, hipStream_t s);
 
 // --------------------------------------------------------------------------
 // Learned threshold (learned.hip).

@@ -607,6 +607,54 @@ __global__ __launch_bounds__(kDmaThreads) void macro_fixup_kernel(float* __restr
     }
 }
 
+// Leaf 128 with N a multiple of 128 on the same kernel: a 128x128 output tile
+// is a macro tile of four 64x64 quarters that all keep every k, so each kept
+// pair (i, k, j) becomes two items (one per 64-wide half of k) with all four
+// membership bits set.  One wave per output tile t: its items at
+// 2 offsets[t] .., and uprefix[t] = 2 offsets[t].
+__global__ __launch_bounds__(256) void leaf128_items_kernel(const int32_t* __restrict__ off,
+                                                            const int32_t* __restrict__ klist, int64_t bdim,
+                                                            int32_t* __restrict__ uprefix,
+                                                            uint32_t* __restrict__ items) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t > bdim * bdim) return;
+    if (lane == 0) uprefix[t] = 2 * off[t];
+    if (t == bdim * bdim) return;
+    const uint32_t i = uint32_t(t / bdim), j = uint32_t(t - (t / bdim) * bdim);
+    for (int32_t q = off[t] + lane; q < off[t + 1]; q += 64) {
+        const uint32_t k = uint32_t(klist[q]);
+        items[2 * int64_t(q)] = mi_pack(i, j, 2 * k, 15u);
+        items[2 * int64_t(q) + 1] = mi_pack(i, j, 2 * k + 1, 15u);
+    }
+}
+
+hipError_t launch_leaf128_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, int32_t* uprefix,
+                                   uint32_t* items, hipStream_t s) {
+    leaf128_items_kernel<<<unsigned((bdim * bdim + 1 + 3) / 4), 256, 0, s>>>(offsets, klist, bdim, uprefix, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf128_multiply(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                                   const int32_t* uprefix, const uint32_t* items, int64_t* bounds, float* fix_slots,
+                                   int num_cus, hipStream_t s) {
+    const int64_t mb = bdim, nm = mb * mb;  // one macro tile per 128x128 output tile
+    const int64_t cap = ((nm + 7) / 8) * 8;
+    static int scratch_state = 0;
+    const hipError_t ce = check_no_scratch(multiply_macro_dma_kernel, &scratch_state);
+    if (ce != hipSuccess) return ce;
+    int64_t groups = int64_t(num_cus);
+    if (groups > cap) groups = cap;
+    groups = ((groups + 7) / 8) * 8;
+    if (groups > kSplitMaxGroups) groups = kSplitMaxGroups;
+    multiply_macro_dma_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, c, n, 2 * mb, mb, items, uprefix,
+                                                                      nullptr, bounds, fix_slots);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || groups < 2) return e;
+    macro_fixup_kernel<<<unsigned(groups - 1), kDmaThreads, 0, s>>>(c, n, mb, uprefix, bounds, fix_slots, groups);
+    return hipGetLastError();
+}
+
 hipError_t launch_macro_schedule(const int32_t* offsets, const int32_t* klist, int64_t bdim, const MacroSchedule& ms,
                                  hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;

@@ -256,19 +256,21 @@ def test_many_pairs_per_workgroup(n, leaf):
     assert rel <= REL_FRO, rel
 
 
+@pytest.mark.parametrize("leaf", [64, 128])
 @pytest.mark.parametrize("kind", ["one_block", "scattered"])
-def test_macro_tiles_shared_between_workgroups(kind):
-    """Leaf 64, N a multiple of 128: the multiply splits its item list between
-    workgroups by cost, so one macro tile can be computed by several
-    workgroups whose partial sums are added by the last to arrive.
-    one_block: all the work sits in one 2x2 block of output tiles (A nonzero
-    in its first 128 rows, B in its first 128 columns), so that block is
-    shared by many workgroups with about one item each; scattered: random
-    tile-level sparsity, many blocks split between two workgroups.  Checked
-    against the oracle, and run twice for bitwise equality (the partials are
-    added in workgroup order, not arrival order)."""
+def test_macro_tiles_shared_between_workgroups(kind, leaf):
+    """Leaf 64 or 128, N a multiple of 128: the multiply splits its item list
+    between workgroups by cost, so one 128x128 macro tile can be computed by
+    several workgroups whose partial sums a second kernel adds (leaf 128: one
+    macro tile per output tile).
+    one_block: all the work sits in one 128x128 block of C (A nonzero in its
+    first 128 rows, B in its first 128 columns), so that block is shared by
+    many workgroups with about one item each; scattered: random tile-level
+    sparsity, many blocks split between two workgroups.  Checked against the
+    oracle, and run twice for bitwise equality (the partials are added in
+    workgroup order)."""
     rng = np.random.default_rng(31)
-    n, leaf, tau = 1024, 64, 1e-6
+    n, tau = 1024, 1e-6
     a, b = inputs.uniform_pm1(n, 41), inputs.uniform_pm1(n, 42)
     if kind == "one_block":
         a[128:, :] = 0.0
