@@ -53,9 +53,10 @@ def multiply_kernel(n: int, leaf: int, precision: str = "fp32", f16x3_staged: bo
         return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", [CSRC / "multiply_lowp.hip", *heads]
     if (leaf == 64 and n % 128 == 0) or (leaf == 128 and n % 128 == 0 and n // 128 <= 512):
         # the launch is two kernels: the multiply, then the split-tile fixup
-        return "multiply_macro_dma_kernel + macro_fixup_kernel", [CSRC / "multiply_macro.hip", *heads]
+        return "multiply_macro_dma_kernel + macro_fixup_kernel", [CSRC / "multiply_macro.hip", CSRC / "macro.h",
+                                                                  *heads]
     if leaf in (32, 64):
-        return f"multiply_macro_kernel<{leaf}", [CSRC / "multiply_macro.hip", *heads]
+        return f"multiply_macro_kernel<{leaf}", [CSRC / "multiply_macro.hip", CSRC / "macro.h", *heads]
     return f"multiply_kernel<{leaf}", [CSRC / "kernels.hip", CSRC / "device.h"]
 
 

@@ -24,15 +24,24 @@ struct BatchPlan {
     size_t header = 0, total = 0;
     std::vector<size_t> base;  // per product region offset
     std::vector<Geom> geom;
-    int64_t tiles = 0, mask_blocks = 0, strips = 0;
+    int64_t tiles = 0, mask_blocks = 0, strips = 0, macros = 0;
     int32_t class_count[spamm::kBatchClasses] = {0, 0, 0};
 };
+
+// macro tiles per side of a product's multiply schedule (leaf 32; 0 for leaf
+// 64 and 128, which run on single tiles: the register-staged macro kernel is
+// slower than the single-tile one for the ragged leaf-64 products of a batch)
+int64_t macro_side(const Geom& g) { return g.leaf == 32 ? (g.bdim + 1) / 2 : 0; }
 
 size_t product_bytes(const Geom& g) {
     const size_t pyr = up(sizeof(double) * size_t(g.pyr));
     const size_t nt = size_t(g.ntiles), b = size_t(g.bdim), nw = size_t(g.nwords);
+    const size_t nm = size_t(macro_side(g)) * size_t(macro_side(g));
+    const size_t macro = nm ? up(sizeof(uint64_t) * nm * 4 * nw) + up(sizeof(int32_t) * nm) +
+                                  up(sizeof(int32_t) * (nm + 1)) + up(sizeof(uint32_t) * nm * b)
+                            : 0;
     return 4 * pyr + up(sizeof(uint64_t) * nt * nw) + up(sizeof(int32_t) * nt) + 2 * up(sizeof(int32_t) * b * nw) +
-           up(sizeof(int32_t) * (nt + 1)) + 2 * up(sizeof(int32_t) * nt * b);
+           up(sizeof(int32_t) * (nt + 1)) + 2 * up(sizeof(int32_t) * nt * b) + macro;
 }
 
 spamm_status plan_batch(int32_t count, const int64_t* n, const int32_t* leaf, BatchPlan* bp) {
@@ -55,6 +64,7 @@ spamm_status plan_batch(int32_t count, const int64_t* n, const int32_t* leaf, Ba
         bp->tiles += g.ntiles;
         bp->mask_blocks += g.bdim * g.nwords;
         bp->strips += g.bdim * ((g.n + kNormCols - 1) / kNormCols);
+        bp->macros += macro_side(g) * macro_side(g);
         ++bp->class_count[leaf_class(leaf[p])];
     }
     bp->total = o;
@@ -86,7 +96,7 @@ spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float
     std::vector<int32_t> members;
     members.reserve(size_t(count));
     char* ws = static_cast<char*>(workspace);
-    int64_t tile_base = 0, mask_base = 0, norm_base = 0;
+    int64_t tile_base = 0, mask_base = 0, norm_base = 0, macro_base = 0;
     for (int32_t p = 0; p < count; ++p) {
         const Geom& g = bp.geom[size_t(p)];
         if ((st = check_mul_args(g, a[p], b[p], c[p])) != SPAMM_OK || (st = check_tau(tau[p])) != SPAMM_OK) {
@@ -112,6 +122,14 @@ spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float
         q.offsets = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (nt + 1)));
         q.klist = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nt * bd));
         q.pair_scratch = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nt * bd));
+        q.mb = macro_side(g);
+        const size_t nm = size_t(q.mb) * size_t(q.mb);
+        if (nm) {
+            q.mwords = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * nm * 4 * nw));
+            q.mcount = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nm));
+            q.mprefix = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (nm + 1)));
+            q.mitems = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * nm * bd));
+        }
         q.a = a[p];
         q.b = b[p];
         q.c = c[p];
@@ -126,6 +144,8 @@ spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float
         q.tile_base = tile_base;
         q.mask_base = mask_base;
         q.norm_base = norm_base;
+        q.macro_base = macro_base;
+        macro_base += q.mb * q.mb;
         tile_base += g.ntiles;
         mask_base += g.bdim * g.nwords;
         norm_base += g.bdim * ((g.n + kNormCols - 1) / kNormCols);
@@ -162,7 +182,7 @@ spamm_status spamm_batch_run(int32_t count, const int64_t* n, const int32_t* lea
     int cus = device_cus();
     cus = (cus + 3) / 4 * 4;  // two groups per CU, a multiple of 8 in all
     return hip_check(spamm::launch_batch(prods, count, members, bp.class_count, class_total, bp.tiles,
-                                         bp.mask_blocks, bp.strips, cus, static_cast<hipStream_t>(stream)),
+                                         bp.mask_blocks, bp.strips, bp.macros, cus, static_cast<hipStream_t>(stream)),
                      "batch kernels");
 }
 

@@ -204,6 +204,14 @@ struct BatchProduct {
     int64_t mask_base;  // prefix of nw * bdim over the batch
     int64_t norm_base;  // prefix of bdim * ceil(n / 1024) (norm-pass strips) over the batch
     int64_t cost_base;  // written on the device: prefix of multiply cost within its leaf class
+    // macro-tile schedule (leaf 32 and 64; mb = 0 for leaf 128): k bitmaps,
+    // union sizes, their prefix, packed items, as in the single-product path
+    uint64_t* mwords;
+    int32_t* mcount;
+    int32_t* mprefix;
+    uint32_t* mitems;
+    int64_t mb;          // macro tiles per side
+    int64_t macro_base;  // prefix of mb^2 over the batch
 };
 
 // leaf classes of the batched multiply: 32, 64, 128
@@ -213,6 +221,7 @@ constexpr int kBatchClasses = 3;
 // class order); class_total receives each class's total multiply cost.
 hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
                         const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
-                        int64_t total_mask_blocks, int64_t total_strips, int num_cus, hipStream_t s);
+                        int64_t total_mask_blocks, int64_t total_strips, int64_t total_macros, int num_cus,
+                        hipStream_t s);
 
 }  // namespace spamm

@@ -11,7 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "dma.h"
 #include "internal.h"
+#include "macro.h"
 
 namespace spamm {
 
@@ -889,20 +891,147 @@ __global__ __launch_bounds__(256) void batch_plan_fill_kernel(const BatchProduct
 
 // per class, the prefix of multiply cost (kPairCost per kept pair + 1 per
 // tile, as in the single-product partition) over its members, in order
-__global__ void batch_cost_kernel(BatchProduct* __restrict__ P, const int32_t* __restrict__ members, int32_t c0,
-                                  int32_t c1, int32_t c2, int64_t* __restrict__ class_total) {
-    const int c = threadIdx.x;
-    if (c >= kBatchClasses) return;
+// Macro-tile schedule of the leaf-32 and leaf-64 products: one wave per macro
+// tile of the batch (prefix macro_base), as macro_words_kernel /
+// macro_items_kernel do for one product, and one block per product for the
+// prefix of union sizes.
+__device__ __forceinline__ int32_t batch_find_macro(const BatchProduct* __restrict__ P, int32_t count, int64_t x) {
+    int32_t lo = 0, hi = count - 1;  // last p with macro_base(p) <= x
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (P[mid].macro_base <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void batch_macro_words_kernel(const BatchProduct* __restrict__ P, int32_t count,
+                                                                int64_t total_macros) {
+    __shared__ unsigned long long sw[4][4][16];  // [wave][tile][word]
+    const int wave = threadIdx.x >> 6;
+    for (int64_t bg = blockIdx.x; bg * 4 < total_macros; bg += gridDim.x) {
+        const int64_t gm = bg * 4 + wave;
+        if (gm >= total_macros) continue;
+        const BatchProduct& q = P[batch_find_macro(P, count, gm)];
+        macro_words_wave(q.offsets, q.klist, q.bdim, q.mb, q.nw, q.mwords, q.mcount, gm - q.macro_base, sw[wave]);
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void batch_macro_scan_kernel(const BatchProduct* __restrict__ P) {
+    const BatchProduct& q = P[blockIdx.x];
+    if (q.mb == 0) return;
+    const int64_t nm = q.mb * q.mb;
+    plan_scan_block(q.mcount, nm, q.mprefix, q.mprefix, nm, nullptr);
+}
+
+__global__ __launch_bounds__(256) void batch_macro_items_kernel(const BatchProduct* __restrict__ P, int32_t count,
+                                                                int64_t total_macros) {
+    const int wave = threadIdx.x >> 6;
+    for (int64_t bg = blockIdx.x; bg * 4 < total_macros; bg += gridDim.x) {
+        const int64_t gm = bg * 4 + wave;
+        if (gm >= total_macros) continue;
+        const BatchProduct& q = P[batch_find_macro(P, count, gm)];
+        macro_items_wave(q.mwords, q.mprefix, q.mb, q.nw, q.mitems, gm - q.macro_base);
+    }
+}
+
+// Cost prefix of each leaf class over its products: leaf 32 runs on macro
+// tiles (kUnionCost per union k + kMacroWrite per macro tile, as the
+// single-product macro kernel), leaf 64 and 128 on single tiles (kPairCost
+// per pair + 1 per tile).  One workgroup; each class's members (contiguous in
+// `members`) are scanned in chunks of kCostThreads.
+constexpr int kCostThreads = 1024;
+__global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchProduct* __restrict__ P,
+                                                                  const int32_t* __restrict__ members, int32_t c0,
+                                                                  int32_t c1, int32_t c2,
+                                                                  int64_t* __restrict__ class_total) {
+    __shared__ int64_t wsum[kCostThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int32_t cnt[kBatchClasses] = {c0, c1, c2};
     int32_t first = 0;
-    for (int k = 0; k < c; ++k) first += cnt[k];
-    int64_t run = 0;
-    for (int32_t k = 0; k < cnt[c]; ++k) {
-        BatchProduct& q = P[members[first + k]];
-        q.cost_base = run;
-        run += int64_t(kPairCost) * (*q.pairs) + q.bdim * q.bdim;
+    for (int c = 0; c < kBatchClasses; ++c) {
+        int64_t carry = 0;
+        for (int32_t start = 0; start < cnt[c]; start += kCostThreads) {
+            const int32_t k = start + tid;
+            int64_t cost = 0;
+            BatchProduct* q = k < cnt[c] ? &P[members[first + k]] : nullptr;
+            if (q) {
+                if (q->mb > 0) {
+                    const int64_t nm = q->mb * q->mb;
+                    cost = int64_t(kUnionCost) * q->mprefix[nm] + int64_t(kMacroWrite) * nm;
+                } else {
+                    cost = int64_t(kPairCost) * (*q->pairs) + q->bdim * q->bdim;
+                }
+            }
+            int64_t incl = cost;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int64_t up = __shfl_up(incl, o);
+                if (lane >= o) incl += up;
+            }
+            if (lane == 63) wsum[wave] = incl;
+            __syncthreads();
+            int64_t before = carry;
+            for (int w = 0; w < wave; ++w) before += wsum[w];
+            if (q) q->cost_base = before + incl - cost;
+            int64_t chunk = 0;
+            for (int w = 0; w < kCostThreads / 64; ++w) chunk += wsum[w];
+            __syncthreads();
+            carry += chunk;
+        }
+        if (tid == 0) class_total[c] = carry;
+        first += cnt[c];
     }
-    class_total[c] = run;
+}
+
+// first macro tile m of product q whose cost position reaches g * total / groups
+__device__ __forceinline__ int64_t batch_macro_partition(const BatchProduct& q, int64_t g, int64_t groups,
+                                                         int64_t total) {
+    const int64_t target = g * total, nm = q.mb * q.mb;
+    int64_t lo = 0, hi = nm;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((q.cost_base + int64_t(kUnionCost) * q.mprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Leaf 32 and 64: a persistent grid over the class's macro tiles (all its
+// products in turn), each workgroup a contiguous range of equal cost.
+template <int LEAF>
+__global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_batch_macro_kernel(
+    const BatchProduct* __restrict__ P, const int32_t* __restrict__ members, int32_t nmem,
+    const int64_t* __restrict__ class_total, int cls) {
+    __shared__ __attribute__((aligned(16))) float lds[2 * MacGeom<LEAF>::STAGE];
+    const int64_t groups = gridDim.x;
+    const int64_t bid = blockIdx.x;
+    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+    const int64_t total = class_total[cls];
+    int32_t lo = 0, hi = nmem - 1;  // last member with cost_base * groups <= lg * total
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (P[members[mid]].cost_base * groups <= lg * total)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    for (int32_t k = lo; k < nmem; ++k) {
+        const BatchProduct& q = P[members[k]];
+        if (q.cost_base * groups >= (lg + 1) * total) break;
+        const int64_t m0 = batch_macro_partition(q, lg, groups, total);
+        const int64_t m1 = batch_macro_partition(q, lg + 1, groups, total);
+        if (m0 >= m1) continue;
+        if (q.vec)
+            macro_range<LEAF, true>(q.a, q.b, q.c, q.n, q.bdim, q.mb, q.mitems, q.mprefix, m0, m1, lds);
+        else
+            macro_range<LEAF, false>(q.a, q.b, q.c, q.n, q.bdim, q.mb, q.mitems, q.mprefix, m0, m1, lds);
+        __syncthreads();
+    }
 }
 
 // first tile t of product q whose cost position reaches target / groups
@@ -954,7 +1083,8 @@ __global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_batch
 
 hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
                         const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
-                        int64_t total_mask_blocks, int64_t total_strips, int num_cus, hipStream_t s) {
+                        int64_t total_mask_blocks, int64_t total_strips, int64_t total_macros, int num_cus,
+                        hipStream_t s) {
     auto blocks = [](int64_t work, int64_t cap) { return unsigned(work < cap ? (work > 0 ? work : 1) : cap); };
     batch_norms_kernel<<<dim3{blocks(total_strips, 1 << 20), 2u, 1u}, kNormThreads, 0, s>>>(prods, count,
                                                                                            total_strips);
@@ -963,7 +1093,13 @@ hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t*
                                                                                        total_mask_blocks);
     batch_plan_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
     batch_plan_fill_kernel<<<blocks((total_tiles + 3) / 4, 1 << 20), 256, 0, s>>>(prods, count, total_tiles);
-    batch_cost_kernel<<<1, 64, 0, s>>>(const_cast<BatchProduct*>(prods), members, class_count_host[0],
+    if (total_macros > 0) {
+        const unsigned mblocks = blocks((total_macros + 3) / 4, 1 << 20);
+        batch_macro_words_kernel<<<mblocks, 256, 0, s>>>(prods, count, total_macros);
+        batch_macro_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
+        batch_macro_items_kernel<<<mblocks, 256, 0, s>>>(prods, count, total_macros);
+    }
+    batch_cost_kernel<<<1, kCostThreads, 0, s>>>(const_cast<BatchProduct*>(prods), members, class_count_host[0],
                                        class_count_host[1], class_count_host[2], class_total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -974,8 +1110,8 @@ hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t*
             const unsigned groups = unsigned(num_cus * 2);
             switch (c) {
                 case 0:
-                    multiply_batch_kernel<32><<<groups, kMulThreads, 0, s>>>(prods, members + first, nmem,
-                                                                             class_total, c);
+                    multiply_batch_macro_kernel<32><<<unsigned(num_cus * MacGeom<32>::OCC), kMacThreads, 0, s>>>(
+                        prods, members + first, nmem, class_total, c);
                     break;
                 case 1:
                     multiply_batch_kernel<64><<<groups, kMulThreads, 0, s>>>(prods, members + first, nmem,
