@@ -40,15 +40,17 @@ CSRC = ROOT / "paper_2103_13042_amd" / "csrc"
 CALIB_BYTES = 256 << 20  # device copy whose counter readings scale the HBM byte counters
 
 
-F16X3_STAGED_PAIRS_PER_TILE = 25  # the library's choice between the two FP16 hi+lo forms
+# the library's choice between the two forms of reduced-precision products:
+# split planes from this many kept pairs per output tile, else in registers
+LOWP_STAGED_PAIRS_PER_TILE = {"bf16": 16, "f16x3": 25}
 
 
-def multiply_kernel(n: int, leaf: int, precision: str = "fp32", f16x3_staged: bool = False) -> tuple[str, list[Path]]:
+def multiply_kernel(n: int, leaf: int, precision: str = "fp32", staged: bool = False) -> tuple[str, list[Path]]:
     """Name and source files (kernel file and the headers it includes) of the
     multiply kernel the timed step launches."""
     heads = [CSRC / "device.h", CSRC / "dma.h"]
-    if precision == "f16x3" and not f16x3_staged:  # hi/lo split in registers from the FP32 tiles
-        return "multiply_f16x3_fused_kernel", [CSRC / "multiply_lowp.hip", *heads]
+    if precision != "fp32" and not staged:  # conversion in registers from the FP32 tiles
+        return f"multiply_fused_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", [CSRC / "multiply_lowp.hip", *heads]
     if precision != "fp32":
         return f"multiply_lowp_kernel<{ {'bf16': 1, 'f16x3': 2}[precision] }>", [CSRC / "multiply_lowp.hip", *heads]
     if (leaf == 64 and n % 128 == 0) or (leaf == 128 and n % 128 == 0 and n // 128 <= 512):
@@ -215,7 +217,7 @@ def main() -> int:
     c = torch.empty_like(a)
     ws = sp.workspace(n, leaf, dev)
     bufs = sp.plan_buffers(n, leaf, dev)
-    split_buf = sp.split_buffer(n, prec, dev) if prec == "bf16" else None
+    split_buf = None
     header = torch.empty(256, dtype=torch.uint8, device=dev) if prec == "f16x3" else None
 
     # a device-to-device copy of known size, for scaling HBM byte counters
@@ -228,32 +230,36 @@ def main() -> int:
     # spamm_execute as its two launch steps, so that events on the stream the
     # library launches on (torch's current stream, passed by the binding)
     # bracket the multiply kernel alone.
-    # BF16 products: the first stage also writes the split operands
-    # (spamm_prepare_split) and the multiply reads them.  FP16 hi+lo: the first
-    # stage adds the scale exponents (spamm_prepare_scales) and the multiply
-    # splits the FP32 tiles in registers (spamm_execute_f16x3_scheduled).
-    # As spamm_multiply_precision does on the device, FP16 hi+lo takes the
-    # split planes when the plan keeps >= 25 pairs per output tile on average
-    # (decided here once, from the pair count of a first pass).
-    f16x3_staged = False
-    if prec == "f16x3":
+    # Reduced-precision products, as spamm_multiply_precision picks on the
+    # device (decided here once, from the pair count of a first pass): with at
+    # least 16 (BF16) or 25 (FP16 hi+lo) kept pairs per output tile on average
+    # the first stage also
+    # writes the split operands (spamm_prepare_split) and the multiply reads
+    # them; below that the multiply converts the FP32 tiles in registers
+    # (BF16: spamm_prepare, spamm_execute_bf16_scheduled; FP16 hi+lo: the first
+    # stage adds the scale exponents, spamm_prepare_scales, then
+    # spamm_execute_f16x3_scheduled).
+    staged = False
+    if prec != "fp32":
         sp.prepare(a, b, tau, leaf, bufs=bufs, ws=ws)
-        f16x3_staged = int(bufs[2].item()) >= F16X3_STAGED_PAIRS_PER_TILE * (n // leaf) ** 2
-        if f16x3_staged:
+        staged = int(bufs[2].item()) >= LOWP_STAGED_PAIRS_PER_TILE[prec] * (n // leaf) ** 2
+        if staged:
             split_buf = sp.split_buffer(n, prec, dev)
 
     def stage_prepare(t):
-        if prec == "fp32":
+        if prec == "fp32" or (prec == "bf16" and not staged):
             return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
-        if prec == "f16x3" and not f16x3_staged:
+        if prec == "f16x3" and not staged:
             return sp.prepare_scales(a, b, t, leaf, header, bufs=bufs, ws=ws)
         return sp.prepare_split(a, b, t, leaf, prec, split_buf, bufs=bufs, ws=ws)
 
     def stage_multiply(offsets, klist):
         if prec == "fp32":
             sp.execute_scheduled(a, b, leaf, offsets, klist, c=c, ws=ws)
-        elif prec == "f16x3" and not f16x3_staged:
+        elif prec == "f16x3" and not staged:
             sp.execute_f16x3(a, b, leaf, header, offsets, klist, c=c, ws=ws)
+        elif prec == "bf16" and not staged:
+            sp.execute_bf16(a, b, leaf, offsets, klist, c=c, ws=ws)
         else:
             sp.execute_split(split_buf, n, leaf, prec, offsets, klist, c=c, ws=ws, scheduled=True)
 
@@ -284,7 +290,7 @@ def main() -> int:
         pairs = int(bufs[2].item())
         return total / steps, stages, pairs
 
-    kname, ksrc = multiply_kernel(n, leaf, prec, f16x3_staged)
+    kname, ksrc = multiply_kernel(n, leaf, prec, staged)
     workload = workload_name(n, leaf, tau, args.workload, args.alpha, prec)
     log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
     ms_step, (prep_ms, sched_ms, kern_ms), pairs = timed(tau, args.steps, args.warmup)

@@ -206,6 +206,17 @@ spamm_status spamm_execute_f16x3_scheduled(const float* a, const float* b, int64
                                            const void* header, const int32_t* offsets, const int32_t* klist,
                                            float* c, void* workspace, size_t workspace_bytes, void* stream);
 
+/* BF16 products (section 3.3's reduced-precision leaf products, FP32
+ * accumulation) straight from the FP32 inputs, after spamm_prepare and
+ * spamm_schedule on the same plan and workspace: one kernel stages FP32 tiles
+ * of A and B and rounds them to BF16 (nearest-even) in registers, so C is
+ * bitwise the C of spamm_split + spamm_execute_split_scheduled with
+ * SPAMM_PREC_BF16, without the split pass over A and B.  a, b: device, 16-byte
+ * aligned; c overwritten.  Errors as spamm_execute_split_scheduled. */
+spamm_status spamm_execute_bf16_scheduled(const float* a, const float* b, int64_t n, int32_t leaf,
+                                          const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
+                                          size_t workspace_bytes, void* stream);
+
 /* spamm_prepare followed by spamm_split_scales on the pyramids it leaves in
  * the workspace (the first stage of the F16X3 path of
  * spamm_multiply_precision).  Errors as spamm_prepare and spamm_split_scales
@@ -223,18 +234,20 @@ spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, doub
                                  int64_t* pairs, void* split, size_t split_bytes, void* workspace,
                                  size_t workspace_bytes, void* stream);
 
-/* The whole path with reduced-precision products.  BF16: spamm_prepare_split,
- * then spamm_execute_split.  F16X3: spamm_prepare_scales into the first 256
- * bytes of `split`, spamm_schedule, then either the planes and the split
- * multiply (spamm_split's planes, spamm_execute_split_scheduled) or the
- * in-register split (spamm_execute_f16x3_scheduled), picked on the device from
- * the plan's pair count: the planes when it keeps at least 25 pairs per output
- * tile on average.  With split_bytes below spamm_split_bytes (at least 256),
- * always in registers and the planes are not written.  Either way C is
- * bitwise the C of the split path.  SPAMM_PREC_FP32 is spamm_multiply (split unused, may be NULL).
- * Errors as spamm_multiply and spamm_split (F16X3: EINVAL for a header that
- * is null, not 256-byte aligned or overlapping a, b or c; ENOSPACE below 256
- * bytes). */
+/* The whole path with reduced-precision products.  F16X3:
+ * spamm_prepare_scales into the first 256 bytes of `split`, spamm_schedule,
+ * then either the planes and the split multiply (spamm_split's planes,
+ * spamm_execute_split_scheduled) or the in-register split
+ * (spamm_execute_f16x3_scheduled), picked on the device from the plan's pair
+ * count: the planes when it keeps at least 25 pairs per output tile on
+ * average.  With split_bytes below spamm_split_bytes (at least 256), always
+ * in registers and the planes are not written.  BF16: the same with
+ * spamm_prepare (no scales) and spamm_execute_bf16_scheduled, the planes from
+ * 16 pairs per tile; split may be NULL (then always in registers).  Either
+ * way C is bitwise the C of the split path.  SPAMM_PREC_FP32 is
+ * spamm_multiply (split unused, may be NULL).  Errors as spamm_multiply and
+ * spamm_split (F16X3: EINVAL for a header that is null, not 256-byte aligned
+ * or overlapping a, b or c; ENOSPACE below 256 bytes). */
 spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
                                       int32_t precision, float* c, int64_t* pairs, void* split, size_t split_bytes,
                                       void* workspace, size_t workspace_bytes, void* stream);

@@ -59,6 +59,7 @@ _SIGS = {
     "spamm_split_scales": (_st, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
     "spamm_prepare_scales": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_execute_f16x3_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_execute_bf16_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare_split": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_multiply_precision": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _vp, _sz, _vp, _sz, _vp]),
     "spamm_batch_workspace_bytes": (_sz, [_i32, _vp, _vp]),
@@ -540,6 +541,24 @@ def execute_f16x3(a, b, leaf: int, header, offsets, klist, *, c=None, ws=None) -
     _check(_lib.spamm_execute_f16x3_scheduled(_ptr(a), _ptr(b), n, leaf, _ptr(header), _ptr(offsets), _ptr(klist),
                                               _ptr(c), _ptr(ws), ws.numel(), _stream(dev)),
            "spamm_execute_f16x3_scheduled")
+    return c
+
+
+def execute_bf16(a, b, leaf: int, offsets, klist, *, c=None, ws=None) -> torch.Tensor:
+    """BF16 products straight from the FP32 inputs after prepare() and
+    schedule() (spamm_execute_bf16_scheduled)."""
+    n = _square_f32(a, "a")
+    if _square_f32(b, "b") != n:
+        raise ValueError("a and b must have the same size")
+    dev = a.device
+    _check_plan(offsets, klist, n, leaf, dev)
+    c = torch.empty_like(a) if c is None else c
+    if _square_f32(c, "c") != n:
+        raise ValueError("c must be n x n")
+    ws = workspace(n, leaf, dev) if ws is None else ws
+    _check(_lib.spamm_execute_bf16_scheduled(_ptr(a), _ptr(b), n, leaf, _ptr(offsets), _ptr(klist), _ptr(c),
+                                             _ptr(ws), ws.numel(), _stream(dev)),
+           "spamm_execute_bf16_scheduled")
     return c
 
 

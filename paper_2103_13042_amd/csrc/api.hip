@@ -243,6 +243,11 @@ constexpr size_t kSplitHeaderBytes = 256;  // scale exponents and largest leaf n
 // about 15 ns per output tile (it reads and writes A and B: 1 ms at
 // N = 16384, 65,536 tiles), so they break even near 25 pairs per tile.
 constexpr int64_t kF16x3StagedPairsPerTile = 25;
+// BF16: the in-register rounding costs 0.5-1.3 ns per kept pair more in the
+// multiply (the FP32 tiles are twice the bytes of the planes), the split pass
+// 11 ns per output tile (measured at N = 16384: break-even at 8 pairs per tile
+// on exponential decay, 22 on the dense ReLU-like pair).
+constexpr int64_t kBf16StagedPairsPerTile = 16;
 size_t plane_bytes(int64_t n) { return (size_t(n) * size_t(n) * 2 + 255) / 256 * 256; }
 int split_planes(int32_t precision) { return precision == spamm::kPrecF16x3 ? 4 : 2; }
 
@@ -521,11 +526,31 @@ spamm_status spamm_execute_f16x3_scheduled(const float* a, const float* b, int64
     if (overlaps(c, sizeof(float) * size_t(n) * size_t(n), header, kSplitHeaderBytes))
         return fail(SPAMM_EINVAL, "c overlaps the header");
     const Layout L = make_layout(g);
-    return hip_check(spamm::launch_f16x3_fused_multiply(a, b, static_cast<const int32_t*>(header), c, n, g.bdim,
-                                                        at<uint32_t>(workspace, L.mitems),
-                                                        at<int32_t>(workspace, L.mprefix), device_cus(),
-                                                        spamm::PairGate{}, static_cast<hipStream_t>(stream)),
+    return hip_check(spamm::launch_fused_multiply(a, b, spamm::kPrecF16x3, static_cast<const int32_t*>(header), c, n,
+                                                  g.bdim, at<uint32_t>(workspace, L.mitems),
+                                                  at<int32_t>(workspace, L.mprefix), device_cus(), spamm::PairGate{},
+                                                  static_cast<hipStream_t>(stream)),
                      "fused f16x3 multiply kernel");
+}
+
+spamm_status spamm_execute_bf16_scheduled(const float* a, const float* b, int64_t n, int32_t leaf,
+                                          const int32_t* offsets, const int32_t* klist, float* c, void* workspace,
+                                          size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!offsets || !klist) return fail(SPAMM_EINVAL, "null pointer");
+    spamm_status st = check_mul_args(g, a, b, c);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_lowp(g, spamm::kPrecBf16)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
+    const Layout L = make_layout(g);
+    return hip_check(spamm::launch_fused_multiply(a, b, spamm::kPrecBf16, nullptr, c, n, g.bdim,
+                                                  at<uint32_t>(workspace, L.mitems),
+                                                  at<int32_t>(workspace, L.mprefix), device_cus(), spamm::PairGate{},
+                                                  static_cast<hipStream_t>(stream)),
+                     "fused bf16 multiply kernel");
 }
 
 spamm_status spamm_prepare_scales(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
@@ -614,10 +639,47 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
                                                         at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),
                             "reduced-precision multiply kernel")) != SPAMM_OK)
             return st;
-        return hip_check(spamm::launch_f16x3_fused_multiply(a, b, SL.exps, c, n, g.bdim,
-                                                            at<uint32_t>(workspace, L.mitems),
-                                                            at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
+        return hip_check(spamm::launch_fused_multiply(a, b, spamm::kPrecF16x3, SL.exps, c, n, g.bdim,
+                                                      at<uint32_t>(workspace, L.mitems),
+                                                      at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
                          "fused f16x3 multiply kernel");
+    }
+    if (precision == spamm::kPrecBf16) {
+        // As for F16X3: with room for the planes the device picks from the
+        // pair count between converting A and B once (many pairs) and
+        // converting the FP32 tiles in registers (few pairs); with only the
+        // header, always in registers.  Both give bitwise the same C.
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
+        const bool planes = split_bytes >= spamm_split_bytes(n, precision);
+        if (planes) {
+            const size_t sb = spamm_split_bytes(n, precision), mbytes = sizeof(float) * size_t(n) * size_t(n);
+            if (!split || overlaps(split, sb, a, mbytes) || overlaps(split, sb, b, mbytes) ||
+                overlaps(split, sb, c, mbytes))
+                return fail(SPAMM_EINVAL, "split buffer null or overlapping a, b or c");
+        }
+        st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
+                           stream);
+        if (st != SPAMM_OK) return st;
+        spamm::PairGate staged{np, kBf16StagedPairsPerTile * g.bdim * g.bdim, 1}, fused{};
+        const spamm::SplitLayout SL = split_layout(split, n, precision);
+        if (planes) {
+            fused = staged;
+            fused.when_at_least = 0;
+            if ((st = hip_check(spamm::launch_split_planes(a, b, n, precision, SL, staged, s), "split kernels")) !=
+                SPAMM_OK)
+                return st;
+        }
+        if ((st = enqueue_schedule(g, offsets, klist, workspace, s)) != SPAMM_OK) return st;
+        if (planes &&
+            (st = hip_check(spamm::launch_lowp_multiply(SL, c, n, g.bdim, precision, at<uint32_t>(workspace, L.mitems),
+                                                        at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),
+                            "reduced-precision multiply kernel")) != SPAMM_OK)
+            return st;
+        return hip_check(spamm::launch_fused_multiply(a, b, spamm::kPrecBf16, nullptr, c, n, g.bdim,
+                                                      at<uint32_t>(workspace, L.mitems),
+                                                      at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
+                         "fused bf16 multiply kernel");
     }
     st = spamm_prepare_split(a, b, n, tau, leaf, precision, offsets, klist, g.ntiles * g.bdim, np, split,
                              split_bytes, workspace, workspace_bytes, stream);

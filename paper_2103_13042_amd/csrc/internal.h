@@ -171,11 +171,13 @@ hipError_t launch_split_planes(const float* a, const float* b, int64_t n, int pr
 // largest leaf norms at header + 8 bytes).
 hipError_t launch_split_scales(int64_t bdim, int lv, const double* pyr_a, const double* pyr_b, int32_t* header,
                                hipStream_t s);
-// f16x3 products straight from the FP32 inputs (the split done in registers),
-// bitwise the same C as launch_split + launch_lowp_multiply.
-hipError_t launch_f16x3_fused_multiply(const float* a, const float* b, const int32_t* exps, float* c, int64_t n,
-                                       int64_t bdim, const uint32_t* items, const int32_t* uprefix, int num_cus,
-                                       const PairGate& gate, hipStream_t s);
+// Reduced-precision products (kPrecBf16 or kPrecF16x3) straight from the FP32
+// inputs (the conversion done in registers), bitwise the same C as
+// launch_split + launch_lowp_multiply.  exps: the split scale exponents
+// (F16X3 only; may be null for BF16).
+hipError_t launch_fused_multiply(const float* a, const float* b, int precision, const int32_t* exps, float* c,
+                                 int64_t n, int64_t bdim, const uint32_t* items, const int32_t* uprefix, int num_cus,
+                                 const PairGate& gate, hipStream_t s);
 hipError_t launch_lowp_multiply(const SplitLayout& L, float* c, int64_t n, int64_t bdim, int precision,
                                 const uint32_t* items, const int32_t* uprefix, int num_cus, const PairGate& gate,
                                 hipStream_t s);

@@ -154,6 +154,8 @@ hipError_t launch_leaf_norms(const NormJob& job, int nmat, int64_t n, int32_t le
 // leaf test keeps.
 
 constexpr int kPyrThreads = 1024;
+constexpr int kPyrLdsTop = 6;                        // highest level kept in LDS
+constexpr int kPyrLdsLevel = 1 << (2 * kPyrLdsTop);  // its node count
 
 __device__ __forceinline__ void pyramid_build(double* __restrict__ sp, double* __restrict__ np, int64_t bdim,
                                               int lv) {
@@ -168,17 +170,28 @@ __device__ __forceinline__ void pyramid_build(double* __restrict__ sp, double* _
             }
         }
     }
+    // levels of at most kPyrLdsLevel nodes (l <= 6) are also kept in LDS, in
+    // buffer l & 1, so the levels above the first such one read their children
+    // there instead of waiting on the global writes of the level below
+    __shared__ double lvl0[kPyrLdsLevel];      // levels 6, 4, 2, 0
+    __shared__ double lvl1[kPyrLdsLevel / 4];  // levels 5, 3, 1
     for (int l = lv - 1; l >= 0; --l) {
         __syncthreads();
         const int64_t w = int64_t(1) << l, cw = 2 * w;
         const int64_t base = level_offset(l), cbase = level_offset(l + 1);
+        // the leaf level (l + 1 == lv) is only in global memory
+        const bool from_lds = l + 1 <= kPyrLdsTop && l + 1 < lv, to_lds = l <= kPyrLdsTop;
+        const double* src = from_lds ? ((l + 1) & 1 ? lvl1 : lvl0) : sp + cbase;
+        double* dst = (l & 1) ? lvl1 : lvl0;
+#pragma unroll 4
         for (int64_t idx = threadIdx.x; idx < w * w; idx += kPyrThreads) {
             const int64_t i = idx >> l, j = idx & (w - 1);
-            const double* c0 = sp + cbase + (2 * i) * cw + 2 * j;
+            const double* c0 = src + (2 * i) * cw + 2 * j;
             const double* c1 = c0 + cw;
             const double v = (c0[0] + c0[1]) + (c1[0] + c1[1]);
             sp[base + idx] = v;
             np[base + idx] = sqrt(v);
+            if (to_lds) dst[idx] = v;
         }
     }
 }

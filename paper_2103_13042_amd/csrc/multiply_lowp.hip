@@ -202,17 +202,20 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// FP16 hi+lo products straight from the FP32 inputs: the copies, LDS stages
-// and swizzles of the FP32 DMA kernel (multiply_macro.hip: A rows of 64
+// Reduced-precision products straight from the FP32 inputs: the copies, LDS
+// stages and swizzles of the FP32 DMA kernel (multiply_macro.hip: A rows of 64
 // floats, chunk c of row r at c ^ (r & 15); B rows of 128 floats, chunk p of
-// row r at p ^ (8 ((r >> 5) & 1))), and at the operand reads the split of
-// split.hip (y = s x, hi = fp16(y), lo = fp16(y - hi), nearest-even) in
-// registers, then the MFMA sequence of multiply_lowp_kernel<kPrecF16x3>: per
-// k-step s4 = 0..3 (k = 16 s4 + 8 (lane >> 5) + 0..7) hi*hi, hi*lo, lo*hi.  The
-// same operand values, the same products in the same order and the same
-// workgroup partition (whole macro tiles) as the split path, so C is
-// bitwise the same, without the split pass's read and write of A and B.
-__global__ __launch_bounds__(kDmaThreads, 1) void multiply_f16x3_fused_kernel(
+// row r at p ^ (8 ((r >> 5) & 1))), and at the operand reads the conversion of
+// split.hip in registers, then the MFMA sequence of multiply_lowp_kernel<MODE>
+// (k-step s4 = 0..3, k = 16 s4 + 8 (lane >> 5) + 0..7):
+//   FP16 hi+lo: y = s x, hi = fp16(y), lo = fp16(y - hi), nearest-even; per
+//     k-step hi*hi, hi*lo, lo*hi;
+//   BF16: bf16(x), nearest-even; one product per k-step.
+// The same operand values, the same products in the same order and the same
+// workgroup partition (whole macro tiles) as the split path, so C is bitwise
+// the same, without the split pass's read and write of A and B.
+template <int MODE>
+__global__ __launch_bounds__(kDmaThreads, 1) void multiply_fused_kernel(
     const float* __restrict__ A, const float* __restrict__ B, const int32_t* __restrict__ exps, float* __restrict__ C,
     int64_t n, int64_t bdim, int64_t mb, const uint32_t* __restrict__ items, const int32_t* __restrict__ uprefix,
     PairGate gate) {
@@ -249,8 +252,9 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_f16x3_fused_kernel(
     const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
     if (m_begin >= m_end) return;
     const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]);
-    const float sa_scale = ldexpf(1.0f, exps[0]), sb_scale = ldexpf(1.0f, exps[1]);
-    const float inv = ldexpf(1.0f, -(exps[0] + exps[1]));
+    constexpr bool F16 = MODE == kPrecF16x3;  // else BF16: no scales (exps may be null)
+    const float sa_scale = F16 ? ldexpf(1.0f, exps[0]) : 1.0f, sb_scale = F16 ? ldexpf(1.0f, exps[1]) : 1.0f;
+    const float inv = F16 ? ldexpf(1.0f, -(exps[0] + exps[1])) : 1.0f;
 
     const uint32_t* ip = items + uprefix[m_begin];
     int64_t pp = 0;
@@ -325,18 +329,26 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_f16x3_fused_kernel(
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 bv[i] = *reinterpret_cast<const float*>(bcol + (16 * s4 + 8 * g + i) * (2 * LEAF * 4));
-            h2 ph[4], pl[4];
-            split2(a0[0], a0[1], sa_scale, ph[0], pl[0]);
-            split2(a0[2], a0[3], sa_scale, ph[1], pl[1]);
-            split2(a1[0], a1[1], sa_scale, ph[2], pl[2]);
-            split2(a1[2], a1[3], sa_scale, ph[3], pl[3]);
-            const h8 ah = cat8(ph[0], ph[1], ph[2], ph[3]), al = cat8(pl[0], pl[1], pl[2], pl[3]);
+            if constexpr (F16) {
+                h2 ph[4], pl[4];
+                split2(a0[0], a0[1], sa_scale, ph[0], pl[0]);
+                split2(a0[2], a0[3], sa_scale, ph[1], pl[1]);
+                split2(a1[0], a1[1], sa_scale, ph[2], pl[2]);
+                split2(a1[2], a1[3], sa_scale, ph[3], pl[3]);
+                const h8 ah = cat8(ph[0], ph[1], ph[2], ph[3]), al = cat8(pl[0], pl[1], pl[2], pl[3]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) split2(bv[2 * i], bv[2 * i + 1], sb_scale, ph[i], pl[i]);
-            const h8 bh = cat8(ph[0], ph[1], ph[2], ph[3]), bl = cat8(pl[0], pl[1], pl[2], pl[3]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc, 0, 0, 0);
+                for (int i = 0; i < 4; ++i) split2(bv[2 * i], bv[2 * i + 1], sb_scale, ph[i], pl[i]);
+                const h8 bh = cat8(ph[0], ph[1], ph[2], ph[3]), bl = cat8(pl[0], pl[1], pl[2], pl[3]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc, 0, 0, 0);
+            } else {
+                const b8 ab = {__bf16(a0[0]), __bf16(a0[1]), __bf16(a0[2]), __bf16(a0[3]),
+                               __bf16(a1[0]), __bf16(a1[1]), __bf16(a1[2]), __bf16(a1[3])};
+                const b8 bb = {__bf16(bv[0]), __bf16(bv[1]), __bf16(bv[2]), __bf16(bv[3]),
+                               __bf16(bv[4]), __bf16(bv[5]), __bf16(bv[6]), __bf16(bv[7])};
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, bb, acc, 0, 0, 0);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -386,19 +398,26 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_f16x3_fused_kernel(
     __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
 }
 
-hipError_t launch_f16x3_fused_multiply(const float* a, const float* b, const int32_t* exps, float* c, int64_t n,
-                                       int64_t bdim, const uint32_t* items, const int32_t* uprefix, int num_cus,
-                                       const PairGate& gate, hipStream_t s) {
+hipError_t launch_fused_multiply(const float* a, const float* b, int precision, const int32_t* exps, float* c,
+                                 int64_t n, int64_t bdim, const uint32_t* items, const int32_t* uprefix, int num_cus,
+                                 const PairGate& gate, hipStream_t s) {
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int64_t cap = ((nm + 7) / 8) * 8;
     int64_t groups = int64_t(num_cus);
     if (groups > cap) groups = cap;
     groups = ((groups + 7) / 8) * 8;
-    static int scratch_state = 0;
-    const hipError_t ce = check_no_scratch(multiply_f16x3_fused_kernel, &scratch_state);
-    if (ce != hipSuccess) return ce;
-    multiply_f16x3_fused_kernel<<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, exps, c, n, bdim, mb, items, uprefix,
-                                                                        gate);
+    static int scratch_bf16 = 0, scratch_f16 = 0;
+    if (precision == kPrecBf16) {
+        const hipError_t ce = check_no_scratch(multiply_fused_kernel<kPrecBf16>, &scratch_bf16);
+        if (ce != hipSuccess) return ce;
+        multiply_fused_kernel<kPrecBf16><<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, exps, c, n, bdim, mb, items,
+                                                                                 uprefix, gate);
+    } else {
+        const hipError_t ce = check_no_scratch(multiply_fused_kernel<kPrecF16x3>, &scratch_f16);
+        if (ce != hipSuccess) return ce;
+        multiply_fused_kernel<kPrecF16x3><<<unsigned(groups), kDmaThreads, 0, s>>>(a, b, exps, c, n, bdim, mb, items,
+                                                                                  uprefix, gate);
+    }
     return hipGetLastError();
 }
 

@@ -111,6 +111,9 @@ def test_staged_split_path_equals_fused(precision):
         assert torch.equal(header[:8], buf[:8])
         sp.schedule(o3, k3, n, leaf, ws=ws)
         assert torch.equal(sp.execute_f16x3(ga, gb, leaf, header, o3, k3, ws=ws), c1)
+    else:  # BF16 rounded in registers from the FP32 tiles: bitwise the same C
+        sp.schedule(offsets, klist, n, leaf, ws=ws)
+        assert torch.equal(sp.execute_bf16(ga, gb, leaf, offsets, klist, ws=ws), c1)
 
 
 def test_f16x3_whole_path_needs_only_the_split_header():
@@ -131,18 +134,20 @@ def test_f16x3_whole_path_needs_only_the_split_header():
     assert e.value.status == 1
 
 
+@pytest.mark.parametrize("precision", ["f16x3", "bf16"])
 @pytest.mark.parametrize("tau", [0.0, 1e-6])
-def test_f16x3_whole_path_picks_either_form_with_the_same_result(tau):
-    # n = 2048, leaf 64: the planes are used at >= 25 pairs per output tile
-    # (tau = 0: 32 per tile), the in-register split below (tau = 1e-6 on this
-    # exponential decay); the header-only call always splits in registers
+def test_whole_path_picks_either_form_with_the_same_result(precision, tau):
+    # n = 2048, leaf 64: the planes are used from 25 (FP16 hi+lo) or 16 (BF16)
+    # pairs per output tile (tau = 0: 32 per tile), the in-register conversion
+    # below (tau = 1e-6 on this exponential decay: 13 per tile); a call with
+    # only 256 bytes of split buffer always converts in registers
     n, leaf = 2048, 64
     a, b = gpu(inputs.exp_decay(n, 0.02, 21)), gpu(inputs.exp_decay(n, 0.02, 22))
-    c_adapt, p_adapt = sp.multiply_precision(a, b, tau, leaf, "f16x3")
-    c_reg, p_reg = sp.multiply_precision(a, b, tau, leaf, "f16x3",
+    c_adapt, p_adapt = sp.multiply_precision(a, b, tau, leaf, precision)
+    c_reg, p_reg = sp.multiply_precision(a, b, tau, leaf, precision,
                                          split_buf=torch.zeros(256, dtype=torch.uint8, device=DEV))
     assert p_adapt == p_reg and torch.equal(c_adapt, c_reg)
-    assert (p_adapt >= 25 * (n // leaf) ** 2) == (tau == 0.0)
+    assert (p_adapt >= {"f16x3": 25, "bf16": 16}[precision] * (n // leaf) ** 2) == (tau == 0.0)
 
 
 def test_zero_and_tau_above_every_product():
