@@ -894,11 +894,21 @@ __global__ __launch_bounds__(kScanThreads) void batch_plan_scan_kernel(const Bat
     plan_scan_block(q.bsums, q.bdim * q.nw, q.boffs, q.offsets, q.bdim * q.bdim, q.pairs);
 }
 
+// Each wave takes kFillRun consecutive tiles of the batch: one search for the
+// product of the first, then a forward walk over the products (in base order;
+// the last of several products with the same base is the one owning the work).
+constexpr int kFillRun = 8;
 __global__ __launch_bounds__(256) void batch_plan_fill_kernel(const BatchProduct* __restrict__ P, int32_t count,
                                                               int64_t total_tiles) {
-    for (int64_t tg = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); tg < total_tiles; tg += int64_t(gridDim.x) * 4) {
-        const BatchProduct& q = P[batch_find(P, count, tg, kFindTile)];
-        plan_fill_wave(q.masks, q.counts, q.boffs, q.bdim, q.offsets, q.klist, tg - q.tile_base);
+    for (int64_t t0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * kFillRun; t0 < total_tiles;
+         t0 += int64_t(gridDim.x) * 4 * kFillRun) {
+        int32_t p = batch_find(P, count, t0, kFindTile);
+        const int64_t t1 = t0 + kFillRun < total_tiles ? t0 + kFillRun : total_tiles;
+        for (int64_t tg = t0; tg < t1; ++tg) {
+            while (p + 1 < count && P[p + 1].tile_base <= tg) ++p;
+            const BatchProduct& q = P[p];
+            plan_fill_wave(q.masks, q.counts, q.boffs, q.bdim, q.offsets, q.klist, tg - q.tile_base);
+        }
     }
 }
 
@@ -920,15 +930,21 @@ __device__ __forceinline__ int32_t batch_find_macro(const BatchProduct* __restri
     return lo;
 }
 
+constexpr int kMacroRun = 4;  // consecutive macro tiles per wave (one search, then a walk)
 __global__ __launch_bounds__(256) void batch_macro_words_kernel(const BatchProduct* __restrict__ P, int32_t count,
                                                                 int64_t total_macros) {
     __shared__ unsigned long long sw[4][4][16];  // [wave][tile][word]
     const int wave = threadIdx.x >> 6;
-    for (int64_t bg = blockIdx.x; bg * 4 < total_macros; bg += gridDim.x) {
-        const int64_t gm = bg * 4 + wave;
-        if (gm >= total_macros) continue;
-        const BatchProduct& q = P[batch_find_macro(P, count, gm)];
-        macro_words_wave(q.offsets, q.klist, q.bdim, q.mb, q.nw, q.mwords, q.mcount, gm - q.macro_base, sw[wave]);
+    for (int64_t m0 = (int64_t(blockIdx.x) * 4 + wave) * kMacroRun; m0 < total_macros;
+         m0 += int64_t(gridDim.x) * 4 * kMacroRun) {
+        int32_t p = batch_find_macro(P, count, m0);
+        const int64_t m1 = m0 + kMacroRun < total_macros ? m0 + kMacroRun : total_macros;
+        for (int64_t gm = m0; gm < m1; ++gm) {
+            while (p + 1 < count && P[p + 1].macro_base <= gm) ++p;
+            const BatchProduct& q = P[p];
+            macro_words_wave(q.offsets, q.klist, q.bdim, q.mb, q.nw, q.mwords, q.mcount, gm - q.macro_base,
+                             sw[wave]);
+        }
     }
 }
 
@@ -942,11 +958,15 @@ __global__ __launch_bounds__(kScanThreads) void batch_macro_scan_kernel(const Ba
 __global__ __launch_bounds__(256) void batch_macro_items_kernel(const BatchProduct* __restrict__ P, int32_t count,
                                                                 int64_t total_macros) {
     const int wave = threadIdx.x >> 6;
-    for (int64_t bg = blockIdx.x; bg * 4 < total_macros; bg += gridDim.x) {
-        const int64_t gm = bg * 4 + wave;
-        if (gm >= total_macros) continue;
-        const BatchProduct& q = P[batch_find_macro(P, count, gm)];
-        macro_items_wave(q.mwords, q.mprefix, q.mb, q.nw, q.mitems, gm - q.macro_base);
+    for (int64_t m0 = (int64_t(blockIdx.x) * 4 + wave) * kMacroRun; m0 < total_macros;
+         m0 += int64_t(gridDim.x) * 4 * kMacroRun) {
+        int32_t p = batch_find_macro(P, count, m0);
+        const int64_t m1 = m0 + kMacroRun < total_macros ? m0 + kMacroRun : total_macros;
+        for (int64_t gm = m0; gm < m1; ++gm) {
+            while (p + 1 < count && P[p + 1].macro_base <= gm) ++p;
+            const BatchProduct& q = P[p];
+            macro_items_wave(q.mwords, q.mprefix, q.mb, q.nw, q.mitems, gm - q.macro_base);
+        }
     }
 }
 
@@ -1105,9 +1125,10 @@ hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t*
     batch_plan_mask_kernel<<<blocks(total_mask_blocks, 1 << 20), kPlanThreads, 0, s>>>(prods, count,
                                                                                        total_mask_blocks);
     batch_plan_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
-    batch_plan_fill_kernel<<<blocks((total_tiles + 3) / 4, 1 << 20), 256, 0, s>>>(prods, count, total_tiles);
+    batch_plan_fill_kernel<<<blocks((total_tiles + 4 * kFillRun - 1) / (4 * kFillRun), 1 << 20), 256, 0, s>>>(
+        prods, count, total_tiles);
     if (total_macros > 0) {
-        const unsigned mblocks = blocks((total_macros + 3) / 4, 1 << 20);
+        const unsigned mblocks = blocks((total_macros + 4 * kMacroRun - 1) / (4 * kMacroRun), 1 << 20);
         batch_macro_words_kernel<<<mblocks, 256, 0, s>>>(prods, count, total_macros);
         batch_macro_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
         batch_macro_items_kernel<<<mblocks, 256, 0, s>>>(prods, count, total_macros);
