@@ -33,11 +33,12 @@ template <int LEAF, bool VEC>
 __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, int64_t n, int64_t bdim, int64_t strip,
                                                  int64_t chunk, double* sumsq, double* norms, int64_t ld) {
     constexpr int G = LEAF / 4;  // threads per tile
-    const int64_t col = chunk * kNormCols + 4 * threadIdx.x;
     const int64_t r0 = strip * LEAF;
     const int64_t r1 = r0 + LEAF < n ? r0 + LEAF : n;
-    double acc0 = 0.0, acc1 = 0.0;
-    if (VEC) {
+    const int t = threadIdx.x;
+    if (VEC) {  // rows 16-byte aligned (n % 4 == 0): columns 4t .. 4t+3 of the chunk
+        const int64_t col = chunk * kNormCols + 4 * t;
+        double acc0 = 0.0, acc1 = 0.0;
         if (col < n) {
             const float* p = x + r0 * n + col;
             int64_t r = r0;
@@ -57,33 +58,106 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
                 acc1 += double(v.z) * double(v.z) + double(v.w) * double(v.w);
             }
         }
-    } else {  // rows not 16-byte aligned: four 4-byte loads per row, row by row
-        if (col < n) {
-            const int lim = int(n - col < 4 ? n - col : 4);
-            const float* p = x + r0 * n + col;
-            for (int64_t r = r0; r < r1; ++r, p += n) {
+        double s = acc0 + acc1;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (e < lim) {
-                        const double v = double(p[e]);
-                        if (e & 1)
-                            acc1 += v * v;
-                        else
-                            acc0 += v * v;
-                    }
-                }
+        for (int off = 1; off < G; off <<= 1) s += __shfl_xor(s, off);
+        const int64_t tj = col / LEAF;
+        if ((t % G) == 0 && tj < bdim) {
+            const int64_t i = strip * ld + tj;
+            if (sumsq) sumsq[i] = s;
+            if (norms) norms[i] = sqrt(s);
+        }
+        return;
+    }
+    // Rows not 16-byte aligned: 16-byte loads at aligned positions of the
+    // flat array.  In row r the chunk starts s = (r n + cb) mod 4 elements past
+    // such a position, so thread t's load holds columns 4t - s .. 4t - s + 3
+    // of the chunk: those below the thread's own tile (first thread of a tile,
+    // s > 0) belong to the tile before it, those below 0 to the previous
+    // chunk (which loads them with its last thread's second load, below).  A
+    // load that would reach past the end of the matrix is done element-wise.
+    const int64_t cb = chunk * kNormCols, nn = n * n;
+    const int lim = int(n - cb < kNormCols ? n - cb : kNormCols);  // columns of this chunk
+    const int home = (4 * t) / LEAF * LEAF;  // first column of the thread's tile
+    double acc_home = 0.0, acc_prev = 0.0;
+    auto add = [&](int64_t q, int c0) {  // the 4 elements at flat q = columns c0 .. c0+3
+        if (c0 + 3 < 0 || c0 >= lim) return;
+        float v[4];
+        if (q + 4 <= nn) {
+            const f4 w = *reinterpret_cast<const f4*>(x + q);
+            v[0] = w.x;
+            v[1] = w.y;
+            v[2] = w.z;
+            v[3] = w.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (q + e < nn) ? x[q + e] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = c0 + e;
+            if (c >= 0 && c < lim) {
+                const double d = double(v[e]);
+                if (c < home)
+                    acc_prev += d * d;
+                else
+                    acc_home += d * d;
             }
         }
+    };
+    // rows whose loads all end inside the matrix (r n + cb + kNormCols + 4 <=
+    // n^2): unconditional loads, the chunk's columns picked by a select
+    const int64_t room = nn - cb - kNormCols - 4;
+    int64_t r_fast = room < 0 ? r0 : room / n + 1;
+    r_fast = r_fast < r0 ? r0 : (r_fast > r1 ? r1 : r_fast);
+    auto take = [&](const f4& w, int c0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = c0 + e;
+            const double d = (c >= 0 && c < lim) ? double(w[e]) : 0.0;
+            if (c < home)
+                acc_prev += d * d;
+            else
+                acc_home += d * d;
+        }
+    };
+#pragma unroll 4
+    for (int64_t r = r0; r < r_fast; ++r) {
+        const int64_t base = r * n + cb;
+        const int s = int(base & 3);
+        take(*reinterpret_cast<const f4*>(x + base - s + 4 * t), 4 * t - s);
     }
-    double s = acc0 + acc1;
+    if (t == kNormThreads - 1) {  // the chunk's last s columns of those rows
+        for (int64_t r = r0; r < r_fast; ++r) {
+            const int64_t base = r * n + cb;
+            const int s = int(base & 3);
+            if (s > 0) take(*reinterpret_cast<const f4*>(x + base - s + kNormCols), kNormCols - s);
+        }
+    }
+    for (int64_t r = r_fast; r < r1; ++r) {  // the matrix's last rows: guarded loads
+        const int64_t base = r * n + cb;
+        const int s = int(base & 3);
+        const int64_t a0 = base - s;
+        add(a0 + 4 * t, 4 * t - s);
+        if (t == kNormThreads - 1 && s > 0) add(a0 + kNormCols, kNormCols - s);
+    }
+    double s = acc_home;
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) s += __shfl_xor(s, off);
-    const int64_t tj = col / LEAF;
-    if ((threadIdx.x % G) == 0 && tj < bdim) {
-        const int64_t t = strip * ld + tj;
-        if (sumsq) sumsq[t] = s;
-        if (norms) norms[t] = sqrt(s);
+    __shared__ double prev[kNormThreads];  // per tile of the chunk: its part held by the next tile's first thread
+    if ((t % G) == 0) prev[t / G] = acc_prev;
+    __syncthreads();
+    if ((t % G) == 0) {
+        const int g = t / G;
+        if (g + 1 < kNormThreads / G) s += prev[g + 1];
+        const int64_t tj = cb / LEAF + g;
+        if (tj < bdim) {
+            const int64_t i = strip * ld + tj;
+            if (sumsq) sumsq[i] = s;
+            if (norms) norms[i] = sqrt(s);
+        }
     }
+    __syncthreads();  // prev is reused by the block's next strip
 }
 
 template <int LEAF, bool VEC>
