@@ -29,7 +29,21 @@ constexpr int kNormCols = kNormThreads * 4;
 
 // strip `strip` (tile row) x column chunk `chunk` of x; tile (strip, tj) goes to
 // sumsq / norms[strip * ld + tj] (either may be null)
-template <int LEAF, bool VEC>
+// NT: nontemporal loads, for a pass whose input is larger than the
+// infinity cache: A and B are read once here, and keeping them out of the
+// caches leaves room for the multiply's tiles (measured on the N = 8192 step:
+// norm pass 112 -> 90 us, multiply unchanged).  Below that size the multiply
+// profits from what the pass leaves in the cache (batch of small products:
+// 2 % slower with NT).
+template <bool NT, typename T>
+__device__ __forceinline__ T load_nt(const T* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <int LEAF, bool VEC, bool NT = false>
 __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, int64_t n, int64_t bdim, int64_t strip,
                                                  int64_t chunk, double* sumsq, double* norms, int64_t ld) {
     constexpr int G = LEAF / 4;  // threads per tile
@@ -44,8 +58,8 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
             int64_t r = r0;
 #pragma unroll 4
             for (; r + 1 < r1; r += 2) {
-                f4 v = *reinterpret_cast<const f4*>(p);
-                f4 w = *reinterpret_cast<const f4*>(p + n);
+                f4 v = load_nt<NT>(reinterpret_cast<const f4*>(p));
+                f4 w = load_nt<NT>(reinterpret_cast<const f4*>(p + n));
                 p += 2 * n;
                 acc0 += double(v.x) * double(v.x) + double(v.y) * double(v.y);
                 acc1 += double(v.z) * double(v.z) + double(v.w) * double(v.w);
@@ -53,7 +67,7 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
                 acc1 += double(w.z) * double(w.z) + double(w.w) * double(w.w);
             }
             if (r < r1) {
-                f4 v = *reinterpret_cast<const f4*>(p);
+                f4 v = load_nt<NT>(reinterpret_cast<const f4*>(p));
                 acc0 += double(v.x) * double(v.x) + double(v.y) * double(v.y);
                 acc1 += double(v.z) * double(v.z) + double(v.w) * double(v.w);
             }
@@ -125,7 +139,7 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
     for (int64_t r = r0; r < r_fast; ++r) {
         const int64_t base = r * n + cb;
         const int s = int(base & 3);
-        take(*reinterpret_cast<const f4*>(x + base - s + 4 * t), 4 * t - s);
+        take(load_nt<NT>(reinterpret_cast<const f4*>(x + base - s + 4 * t)), 4 * t - s);
     }
     if (t == kNormThreads - 1) {  // the chunk's last s columns of those rows
         for (int64_t r = r0; r < r_fast; ++r) {
@@ -160,10 +174,10 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
     __syncthreads();  // prev is reused by the block's next strip
 }
 
-template <int LEAF, bool VEC>
+template <int LEAF, bool VEC, bool NT>
 __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, int64_t n, int64_t bdim) {
     const int m = blockIdx.z;
-    leaf_sumsq_strip<LEAF, VEC>(job.x[m], n, bdim, blockIdx.y, blockIdx.x, job.sumsq[m], job.norms[m], job.ld);
+    leaf_sumsq_strip<LEAF, VEC, NT>(job.x[m], n, bdim, blockIdx.y, blockIdx.x, job.sumsq[m], job.norms[m], job.ld);
 }
 
 // Any other leaf size: one block per tile, strided over its elements.
@@ -193,14 +207,21 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_generic_kernel(NormJo
     }
 }
 
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;  // MI355X's last-level cache
+
 template <int LEAF>
 static hipError_t launch_leaf_fixed(const NormJob& job, int nmat, int64_t n, int64_t bdim, bool vec,
                                     hipStream_t s) {
     dim3 grid(unsigned((n + kNormCols - 1) / kNormCols), unsigned(bdim), unsigned(nmat));
-    if (vec)
-        leaf_sumsq_kernel<LEAF, true><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
+    const bool nt = 4.0 * double(n) * double(n) * nmat > kInfinityCacheBytes;
+    if (vec && nt)
+        leaf_sumsq_kernel<LEAF, true, true><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
+    else if (vec)
+        leaf_sumsq_kernel<LEAF, true, false><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
+    else if (nt)
+        leaf_sumsq_kernel<LEAF, false, true><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
     else
-        leaf_sumsq_kernel<LEAF, false><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
+        leaf_sumsq_kernel<LEAF, false, false><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
     return hipGetLastError();
 }
 
