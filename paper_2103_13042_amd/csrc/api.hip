@@ -605,86 +605,47 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
     int32_t* offsets = at<int32_t>(workspace, L.offsets);
     int32_t* klist = at<int32_t>(workspace, L.klist);
     int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
-    if (precision == spamm::kPrecF16x3) {
-        // With room for the planes the device picks, from the plan's pair
-        // count, between splitting A and B once and multiplying the planes
-        // (many pairs: each tile feeds many products) and splitting the FP32
-        // tiles in registers inside the multiply (few pairs: the split pass
-        // would cost more than the conversions).  With only the header, always
-        // in registers.  Both give bitwise the same C.
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
-        const bool planes = split_bytes >= spamm_split_bytes(n, precision);
-        if (planes) {
-            const size_t sb = spamm_split_bytes(n, precision), mbytes = sizeof(float) * size_t(n) * size_t(n);
-            if (!split || overlaps(split, sb, a, mbytes) || overlaps(split, sb, b, mbytes) ||
-                overlaps(split, sb, c, mbytes))
-                return fail(SPAMM_EINVAL, "split buffer null or overlapping a, b or c");
-        }
-        st = spamm_prepare_scales(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, split, split_bytes,
-                                  workspace, workspace_bytes, stream);
-        if (st != SPAMM_OK) return st;
-        spamm::PairGate staged{np, kF16x3StagedPairsPerTile * g.bdim * g.bdim, 1}, fused{};
-        const spamm::SplitLayout SL = split_layout(split, n, precision);
-        if (planes) {
-            fused = staged;
-            fused.when_at_least = 0;
-            if ((st = hip_check(spamm::launch_split_planes(a, b, n, precision, SL, staged, s), "split kernels")) !=
-                SPAMM_OK)
-                return st;
-        }
-        if ((st = enqueue_schedule(g, offsets, klist, workspace, s)) != SPAMM_OK) return st;
-        if (planes &&
-            (st = hip_check(spamm::launch_lowp_multiply(SL, c, n, g.bdim, precision, at<uint32_t>(workspace, L.mitems),
-                                                        at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),
-                            "reduced-precision multiply kernel")) != SPAMM_OK)
-            return st;
-        return hip_check(spamm::launch_fused_multiply(a, b, spamm::kPrecF16x3, SL.exps, c, n, g.bdim,
-                                                      at<uint32_t>(workspace, L.mitems),
-                                                      at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
-                         "fused f16x3 multiply kernel");
+    // With room for the planes the device picks, from the plan's pair count,
+    // between converting A and B once and multiplying the planes (many pairs:
+    // each tile feeds many products) and converting the FP32 tiles in
+    // registers inside the multiply (few pairs: the split pass would cost more
+    // than the conversions).  With less room (F16X3: only the 256-byte header
+    // of scale exponents), always in registers.  Both give bitwise the same C.
+    const bool f16 = precision == spamm::kPrecF16x3;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
+    const bool planes = split_bytes >= spamm_split_bytes(n, precision);
+    if (planes) {
+        const size_t sb = spamm_split_bytes(n, precision), mbytes = sizeof(float) * size_t(n) * size_t(n);
+        if (!split || overlaps(split, sb, a, mbytes) || overlaps(split, sb, b, mbytes) ||
+            overlaps(split, sb, c, mbytes))
+            return fail(SPAMM_EINVAL, "split buffer null or overlapping a, b or c");
     }
-    if (precision == spamm::kPrecBf16) {
-        // As for F16X3: with room for the planes the device picks from the
-        // pair count between converting A and B once (many pairs) and
-        // converting the FP32 tiles in registers (few pairs); with only the
-        // header, always in registers.  Both give bitwise the same C.
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        if (!aligned16(a) || !aligned16(b)) return fail(SPAMM_EINVAL, "a and b need 16-byte alignment");
-        const bool planes = split_bytes >= spamm_split_bytes(n, precision);
-        if (planes) {
-            const size_t sb = spamm_split_bytes(n, precision), mbytes = sizeof(float) * size_t(n) * size_t(n);
-            if (!split || overlaps(split, sb, a, mbytes) || overlaps(split, sb, b, mbytes) ||
-                overlaps(split, sb, c, mbytes))
-                return fail(SPAMM_EINVAL, "split buffer null or overlapping a, b or c");
-        }
-        st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
-                           stream);
-        if (st != SPAMM_OK) return st;
-        spamm::PairGate staged{np, kBf16StagedPairsPerTile * g.bdim * g.bdim, 1}, fused{};
-        const spamm::SplitLayout SL = split_layout(split, n, precision);
-        if (planes) {
-            fused = staged;
-            fused.when_at_least = 0;
-            if ((st = hip_check(spamm::launch_split_planes(a, b, n, precision, SL, staged, s), "split kernels")) !=
-                SPAMM_OK)
-                return st;
-        }
-        if ((st = enqueue_schedule(g, offsets, klist, workspace, s)) != SPAMM_OK) return st;
-        if (planes &&
-            (st = hip_check(spamm::launch_lowp_multiply(SL, c, n, g.bdim, precision, at<uint32_t>(workspace, L.mitems),
-                                                        at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),
-                            "reduced-precision multiply kernel")) != SPAMM_OK)
-            return st;
-        return hip_check(spamm::launch_fused_multiply(a, b, spamm::kPrecBf16, nullptr, c, n, g.bdim,
-                                                      at<uint32_t>(workspace, L.mitems),
-                                                      at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
-                         "fused bf16 multiply kernel");
-    }
-    st = spamm_prepare_split(a, b, n, tau, leaf, precision, offsets, klist, g.ntiles * g.bdim, np, split,
-                             split_bytes, workspace, workspace_bytes, stream);
+    st = f16 ? spamm_prepare_scales(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, split, split_bytes,
+                                    workspace, workspace_bytes, stream)
+             : spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
+                             stream);
     if (st != SPAMM_OK) return st;
-    return spamm_execute_split(split, n, leaf, precision, offsets, klist, c, workspace, workspace_bytes, stream);
+    const int64_t per_tile = f16 ? kF16x3StagedPairsPerTile : kBf16StagedPairsPerTile;
+    spamm::PairGate staged{np, per_tile * g.bdim * g.bdim, 1}, fused{};
+    const spamm::SplitLayout SL = split_layout(split, n, precision);
+    if (planes) {
+        fused = staged;
+        fused.when_at_least = 0;
+        if ((st = hip_check(spamm::launch_split_planes(a, b, n, precision, SL, staged, s), "split kernels")) !=
+            SPAMM_OK)
+            return st;
+    }
+    if ((st = enqueue_schedule(g, offsets, klist, workspace, s)) != SPAMM_OK) return st;
+    if (planes &&
+        (st = hip_check(spamm::launch_lowp_multiply(SL, c, n, g.bdim, precision, at<uint32_t>(workspace, L.mitems),
+                                                    at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),
+                        "reduced-precision multiply kernel")) != SPAMM_OK)
+        return st;
+    return hip_check(spamm::launch_fused_multiply(a, b, precision, f16 ? SL.exps : nullptr, c, n, g.bdim,
+                                                  at<uint32_t>(workspace, L.mitems),
+                                                  at<int32_t>(workspace, L.mprefix), device_cus(), fused, s),
+                     "reduced-precision multiply kernel (in-register conversion)");
 }
 
 spamm_status spamm_search_valid_ratio(const double* pyr_a, const double* pyr_b, int64_t n, int32_t leaf,
