@@ -90,8 +90,11 @@ def parse_args():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--tau", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["alg", "exp", "relu", "batch"], default="alg",
-                    help="matrix family (default: algebraic decay); batch: 256 independent products")
+    ap.add_argument("--workload", choices=["alg", "exp", "relu", "paper", "batch"], default="alg",
+                    help="matrix family (default: algebraic decay); paper: the paper's evaluation matrix "
+                         "0.1/(|i-j|^0.1+1) with tau from the valid-ratio search; batch: 256 independent products")
+    ap.add_argument("--valid-ratio", type=float, default=0.1,
+                    help="with --workload paper: the valid ratio the threshold search aims at")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-leaf", type=int, default=0, help="one leaf for every product (0: autotuned)")
     ap.add_argument("--retune", default="", help="re-run the leaf tuner and write its table to this path")
@@ -167,6 +170,7 @@ def workload_name(n: int, leaf: int, tau: float, kind: str = "alg", alpha: float
         "alg": "algebraic-decay s_ij/(1+|i-j|)^2",
         "exp": f"exponential-decay exp(-{alpha:g}|i-j|)(0.5+0.5u)",
         "relu": "ReLU-like (60% zeros, N(0,1) clipped at 0)",
+        "paper": "paper matrix 0.1/(|i-j|^0.1+1) (A = B)",
     }[kind]
     name = f"{base}, N={n}, leaf {leaf}, tau={tau:g}"
     return name if precision == "fp32" else f"{name}, {precision} leaf products"
@@ -210,10 +214,19 @@ def main() -> int:
     else:  # generated on the device; the CPU baseline reads them back
         if args.workload == "exp":
             a, b = inputs.exp_decay_torch(n, args.alpha, 0, dev), inputs.exp_decay_torch(n, args.alpha, 1, dev)
+        elif args.workload == "paper":
+            a = inputs.paper_algebraic_torch(n, dev)
+            b = a.clone()
         else:
             a, b = inputs.relu_like_torch(n, 0, dev), inputs.relu_like_torch(n, 1, dev)
         a_np = b_np = None
     log(f"inputs ready in {time.perf_counter() - t0:.1f}s")
+    if args.workload == "paper":  # tau for the requested valid ratio (section 3.5.2's search)
+        pa, pb = sp.pyramid(a, leaf), sp.pyramid(b, leaf)
+        tau, found, iters = sp.search_valid_ratio(pa, pb, n, leaf, args.valid_ratio)
+        log(f"valid-ratio search: tau={tau:.6g} keeps {found} of {bd ** 3} triples "
+            f"({100.0 * found / bd ** 3:.2f} %, target {100.0 * args.valid_ratio:g} %) in {iters} bisections")
+        del pa, pb
     c = torch.empty_like(a)
     ws = sp.workspace(n, leaf, dev)
     bufs = sp.plan_buffers(n, leaf, dev)

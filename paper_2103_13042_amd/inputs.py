@@ -97,6 +97,17 @@ def paper_algebraic(n: int) -> np.ndarray:
     return out
 
 
+def paper_algebraic_torch(n: int, device):
+    """paper_algebraic(n) built on the device from the same float32 band (bitwise
+    the host generator's entries, without an N^2 host array)."""
+    import torch
+
+    v = torch.from_numpy(paper_algebraic_band(n)).to(device)
+    w = torch.cat([v.flip(0), v[1:]])  # w[m] = v[|m - (n-1)|]
+    # y[i, j'] = w[i + j'];  x[i, j] = y[i, n-1-j] = w[i - j + n - 1] = v[|i - j|]
+    return torch.as_strided(w, (n, n), (1, 1)).flip(1).contiguous()
+
+
 def uniform_pm1(n: int, seed: int) -> np.ndarray:
     """Dense test matrix, entries uniform in [-1, 1)."""
     return _build(n, lambda r, c, d: 2.0 * uniform01(seed, r, c) - 1.0)

@@ -27,12 +27,8 @@ def gpu(x: np.ndarray) -> torch.Tensor:
 
 
 def toeplitz_on_device(n: int) -> torch.Tensor:
-    """paper_algebraic(n) built on the device from the same float32 band, so the
-    entries are bitwise those of the host generator without an N^2 host copy."""
-    v = torch.from_numpy(inputs.paper_algebraic_band(n)).to(DEV)
-    w = torch.cat([v.flip(0), v[1:]])  # w[m] = v[|m - (n-1)|]
-    # y[i, j'] = w[i + j'];  x[i, j] = y[i, n-1-j] = w[i - j + n - 1] = v[|i - j|]
-    return torch.as_strided(w, (n, n), (1, 1)).flip(1).contiguous()
+    """paper_algebraic(n) built on the device (inputs.paper_algebraic_torch)."""
+    return inputs.paper_algebraic_torch(n, DEV)
 
 
 def test_device_toeplitz_matches_host_generator():
