@@ -529,8 +529,20 @@ def cpu_baseline_batch(a_l, b_l, leaves, tau, specs, budget_s):
         if t_all >= budget_s:
             break
     return {"value": flop / t_all / 1e12, "unit": "TFLOP/s (dense-equivalent sum of 2N^3 / t)",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": oracle.max_threads(), "kind": "oracle", "cpu": host_cpu(),
             "sample": f"FP64 oracle on {done} of {len(specs)} products (whole products, seeded order), {t_all:.1f}s"}
+
+
+def host_cpu() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), for the CPU-baseline record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(a_np, b_np, c_gpu, tau, leaf, budget_s):
@@ -587,7 +599,7 @@ def cpu_baseline(a_np, b_np, c_gpu, tau, leaf, budget_s):
     log(f"cpu baseline: {sample}")
     return (
         {"value": value, "unit": "TFLOP/s (dense-equivalent 2N^3/t)", "cores": oracle.max_threads(),
-         "kind": "oracle", "sample": sample},
+         "kind": "oracle", "cpu": host_cpu(), "sample": sample},
         rel,
     )
 
