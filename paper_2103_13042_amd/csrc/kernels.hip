@@ -83,29 +83,34 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
         }
         return;
     }
-    // Rows not 16-byte aligned: 16-byte loads at aligned positions of the
-    // flat array.  In row r the chunk starts s = (r n + cb) mod 4 elements past
-    // such a position, so thread t's load holds columns 4t - s .. 4t - s + 3
-    // of the chunk: those below the thread's own tile (first thread of a tile,
-    // s > 0) belong to the tile before it, those below 0 to the previous
-    // chunk (which loads them with its last thread's second load, below).  A
-    // load that would reach past the end of the matrix is done element-wise.
-    const int64_t cb = chunk * kNormCols, nn = n * n;
+    // Rows not 16-byte aligned (n % 4 != 0, or x itself only 4-byte aligned):
+    // 16-byte loads at aligned positions, counted from xa, the 16-byte
+    // boundary at or below x (xoff floats before it, inside the same
+    // allocation since allocations are at least 16-byte aligned).  In row r
+    // the chunk starts s = (xoff + r n + cb) mod 4 elements past such a
+    // position, so thread t's load holds columns 4t - s .. 4t - s + 3 of the
+    // chunk: those below the thread's own tile (first thread of a tile, s > 0)
+    // belong to the tile before it, those below 0 to the previous chunk (which
+    // loads them with its last thread's second load, below).  A load that
+    // would reach past the end of the matrix is done element-wise.
+    const int xoff = int((reinterpret_cast<uintptr_t>(x) >> 2) & 3);
+    const float* xa = x - xoff;
+    const int64_t cb = chunk * kNormCols, nn = n * n, end = nn + xoff;  // end: counted from xa
     const int lim = int(n - cb < kNormCols ? n - cb : kNormCols);  // columns of this chunk
     const int home = (4 * t) / LEAF * LEAF;  // first column of the thread's tile
     double acc_home = 0.0, acc_prev = 0.0;
-    auto add = [&](int64_t q, int c0) {  // the 4 elements at flat q = columns c0 .. c0+3
+    auto add = [&](int64_t q, int c0) {  // the 4 elements at xa[q ..] = columns c0 .. c0+3
         if (c0 + 3 < 0 || c0 >= lim) return;
         float v[4];
-        if (q + 4 <= nn) {
-            const f4 w = *reinterpret_cast<const f4*>(x + q);
+        if (q + 4 <= end) {
+            const f4 w = *reinterpret_cast<const f4*>(xa + q);
             v[0] = w.x;
             v[1] = w.y;
             v[2] = w.z;
             v[3] = w.w;
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (q + e < nn) ? x[q + e] : 0.0f;
+            for (int e = 0; e < 4; ++e) v[e] = (q + e < end) ? xa[q + e] : 0.0f;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -137,19 +142,19 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
     };
 #pragma unroll 4
     for (int64_t r = r0; r < r_fast; ++r) {
-        const int64_t base = r * n + cb;
+        const int64_t base = xoff + r * n + cb;
         const int s = int(base & 3);
-        take(load_nt<NT>(reinterpret_cast<const f4*>(x + base - s + 4 * t)), 4 * t - s);
+        take(load_nt<NT>(reinterpret_cast<const f4*>(xa + base - s + 4 * t)), 4 * t - s);
     }
     if (t == kNormThreads - 1) {  // the chunk's last s columns of those rows
         for (int64_t r = r0; r < r_fast; ++r) {
-            const int64_t base = r * n + cb;
+            const int64_t base = xoff + r * n + cb;
             const int s = int(base & 3);
-            if (s > 0) take(*reinterpret_cast<const f4*>(x + base - s + kNormCols), kNormCols - s);
+            if (s > 0) take(*reinterpret_cast<const f4*>(xa + base - s + kNormCols), kNormCols - s);
         }
     }
     for (int64_t r = r_fast; r < r1; ++r) {  // the matrix's last rows: guarded loads
-        const int64_t base = r * n + cb;
+        const int64_t base = xoff + r * n + cb;
         const int s = int(base & 3);
         const int64_t a0 = base - s;
         add(a0 + 4 * t, 4 * t - s);

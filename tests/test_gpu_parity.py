@@ -92,11 +92,12 @@ def check_c(c_gpu: np.ndarray, a, b, tau, leaf, c_ref=None):
 
 @pytest.mark.parametrize(
     "n,leaf,offset",
-    [(1024, 32, 0), (1000, 64, 0), (1001, 32, 0), (1024, 64, 1), (300, 128, 0), (77, 16, 0), (130, 7, 0), (5, 8, 0)],
+    [(1024, 32, 0), (1000, 64, 0), (1001, 32, 0), (1024, 64, 1), (1024, 128, 2), (1001, 32, 3), (2050, 64, 1),
+     (300, 128, 0), (77, 16, 0), (130, 7, 0), (5, 8, 0)],
 )
 def test_leaf_norms_match_oracle(n, leaf, offset):
     a = inputs.exp_decay(n, 0.05, 0)
-    if offset:  # a view that is not 16-byte aligned takes the scalar load path
+    if offset:  # a view that is only 4-byte aligned takes the path for unaligned rows
         buf = torch.zeros(n * n + offset, dtype=torch.float32, device=DEV)
         buf[offset:] = gpu(a).reshape(-1)
         x = buf[offset:].view(n, n)
