@@ -107,3 +107,33 @@ def test_batch_argument_errors():
         sp.Batch([a], [torch.ones(32, 32, device=DEV)], [32], [1e-6])
     with pytest.raises(sp.SpammError):
         sp.Batch([a, a], [a, a], [32, 64], [1e-6, 1e-6], c_list=[a, torch.ones(64, 64, device=DEV)])  # c aliases a
+
+
+def _offset_view(x: np.ndarray, offset: int) -> torch.Tensor:
+    n = x.shape[0]
+    buf = torch.zeros(n * n + offset, dtype=torch.float32, device=DEV)
+    buf[offset:] = torch.from_numpy(x).to(DEV).reshape(-1)
+    return buf[offset:].view(n, n)
+
+
+def test_batch_with_members_that_are_only_4_byte_aligned():
+    """Members whose A and B start 4, 8 or 12 bytes past a 16-byte boundary sit
+    beside aligned ones in every leaf class; each takes the unaligned norm and
+    multiply paths and must still equal the oracle."""
+    specs = [(640, 32, 1), (640, 32, 0), (1024, 64, 2), (512, 64, 0), (777, 128, 3), (1000, 64, 1)]
+    mats = [inputs.exp_decay(n, 0.05, 60 + q) for q, (n, _, _) in enumerate(specs)]
+    matsb = [inputs.exp_decay(n, 0.08, 70 + q) for q, (n, _, _) in enumerate(specs)]
+    ga = [_offset_view(a, off) if off else torch.from_numpy(a).to(DEV) for a, (_, _, off) in zip(mats, specs)]
+    gb = [_offset_view(b, off) if off else torch.from_numpy(b).to(DEV) for b, (_, _, off) in zip(matsb, specs)]
+    tau = 1e-6
+    bt = sp.Batch(ga, gb, [s[1] for s in specs], [tau] * len(specs))
+    bt.run()
+    torch.cuda.synchronize()
+    pairs = bt.pairs.cpu().tolist()
+    for q, ((n, leaf, _), a, b) in enumerate(zip(specs, mats, matsb)):
+        c_ref, count, _ = oracle.spamm(a, b, tau, leaf)
+        abs_ref, _, _ = oracle.spamm(np.abs(a), np.abs(b), tau, leaf)
+        assert pairs[q] == count, q
+        bound = n * U32 / (1 - n * U32) * abs_ref + 1e-38
+        c = bt.c[q].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(c - c_ref) <= bound), q

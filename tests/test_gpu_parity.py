@@ -228,6 +228,34 @@ def test_multiply_matches_oracle(n, leaf, q, kind):
     check_c(c.cpu().numpy(), a, b, tau, leaf, c_ref=c_ref)
 
 
+def _offset_view(x: np.ndarray, offset: int) -> torch.Tensor:
+    """x on the GPU as a view that starts `offset` floats into its buffer."""
+    n = x.shape[0]
+    buf = torch.zeros(n * n + offset, dtype=torch.float32, device=DEV)
+    buf[offset:] = gpu(x).reshape(-1)
+    return buf[offset:].view(n, n)
+
+
+@pytest.mark.parametrize("n,leaf,offset", [(1024, 64, 1), (1024, 32, 2), (1024, 128, 3), (1000, 64, 1)])
+def test_multiply_on_views_that_are_only_4_byte_aligned(n, leaf, offset):
+    """A and B start 4, 8 or 12 bytes past a 16-byte boundary: the norm pass and
+    the multiply take their paths for unaligned operands, and C must be the
+    oracle's and the same, bitwise in the pair count and to the accumulation
+    bound in C, as for the aligned copies."""
+    a, b = inputs.exp_decay(n, 0.02, 8), inputs.exp_decay(n, 0.02, 9)
+    prod = oracle_products(a, b, leaf)
+    tau = float(np.quantile(prod, 0.5))
+    c_ref, count, _ = oracle.spamm(a, b, tau, leaf)
+    ga, gb = _offset_view(a, offset), _offset_view(b, offset)
+    assert ga.data_ptr() % 16 != 0 and gb.data_ptr() % 16 != 0
+    c, pairs = sp.multiply(ga, gb, tau, leaf)
+    if off_tie(prod, tau).all():
+        assert pairs == count
+    check_c(c.cpu().numpy(), a, b, tau, leaf, c_ref=c_ref)
+    c_al, pairs_al = sp.multiply(gpu(a), gpu(b), tau, leaf)
+    assert pairs_al == pairs
+
+
 def test_tau_zero_is_dense_and_counts_every_triple():
     n, leaf = 512, 64
     a, b = inputs.uniform_pm1(n, 1), inputs.uniform_pm1(n, 2)
