@@ -18,8 +18,8 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 LIB = PKG / "libspamm.so"
-SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "multiply_lowp.hip", CSRC / "split.hip", CSRC / "learned.hip",
-           CSRC / "api.hip", CSRC / "api_tau.hip", CSRC / "api_batch.hip"]
+SOURCES = [CSRC / "kernels.hip", CSRC / "multiply_macro.hip", CSRC / "multiply_lowp.hip", CSRC / "multiply_small.hip",
+           CSRC / "split.hip", CSRC / "learned.hip", CSRC / "api.hip", CSRC / "api_tau.hip", CSRC / "api_batch.hip"]
 ARCH = "gfx950"
 
 

@@ -419,6 +419,30 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
     return enqueue_plan(g, pa, pb, tau, false, offsets, klist, pairs, workspace, s);
 }
 
+namespace {
+// Small products: the leaf norm pass (which also clears the pair counter),
+// then the threshold test and the multiply in one launch.
+spamm_status enqueue_small(const Geom& g, const float* a, const float* b, double tau, float* c, int64_t* pairs,
+                           void* ws, hipStream_t s) {
+    const Layout L = make_layout(g);
+    const int64_t leaf_level = spamm::level_offset(g.lv);
+    spamm::NormJob nj{};
+    nj.ld = g.side;
+    nj.clear = pairs;
+    const float* xs[2] = {a, b};
+    for (int m = 0; m < 2; ++m) {
+        nj.x[m] = xs[m];
+        nj.sumsq[m] = at<double>(ws, L.spyr[m]) + leaf_level;
+        nj.norms[m] = at<double>(ws, L.pyr[m]) + leaf_level;
+    }
+    spamm_status st = hip_check(spamm::launch_leaf_norms(nj, 2, g.n, g.leaf, true, s), "leaf norm kernel");
+    if (st != SPAMM_OK) return st;
+    return hip_check(spamm::launch_small_multiply(a, b, c, g.n, g.bdim, nj.norms[0], nj.norms[1], g.side, tau, pairs,
+                                                  s),
+                     "small multiply kernel");
+}
+}  // namespace
+
 spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,
                             int64_t* pairs, void* workspace, size_t workspace_bytes, void* stream) {
     g_last_error[0] = '\0';
@@ -430,9 +454,11 @@ spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double ta
     if ((st = check_grid(g)) != SPAMM_OK) return st;
     if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
     const Layout L = make_layout(g);
+    int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
+    if (g.leaf == 32 && g.bdim <= spamm::kSmallMaxBdim && g.n % 4 == 0 && aligned16(a) && aligned16(b))
+        return enqueue_small(g, a, b, tau, c, np, workspace, static_cast<hipStream_t>(stream));
     int32_t* offsets = at<int32_t>(workspace, L.offsets);
     int32_t* klist = at<int32_t>(workspace, L.klist);
-    int64_t* np = pairs ? pairs : at<int64_t>(workspace, L.pairs);
     st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
                        stream);
     if (st != SPAMM_OK) return st;

@@ -18,6 +18,7 @@ struct NormJob {
     double* sumsq[2];  // leaf sums of squares, row stride ld, or null
     double* norms[2];  // leaf norms, row stride ld, or null
     int64_t ld;        // row stride of the outputs (bdim, or the padded pyramid side)
+    int64_t* clear;    // one device int64 set to zero by the launch, or null
 };
 
 // The leaf level of both pyramids is written by the norm pass (stride = side);
@@ -53,6 +54,15 @@ hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t*
 // compaction of its bitmap into an ascending k-list.
 hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* counts, const int32_t* block_offsets,
                             int64_t bdim, int32_t* offsets, int32_t* klist, hipStream_t s);
+
+// Small products (leaf 32, bdim <= kSmallMaxBdim, n % 4 == 0, a and b 16-byte
+// aligned): the threshold test on the leaf norms na / nb (row stride ld) and
+// the multiply of the kept pairs in one launch; adds the number of kept pairs
+// to *pairs, which must be zero before (the norm pass clears it).
+constexpr int64_t kSmallMaxBdim = 64;
+hipError_t launch_small_multiply(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                                 const double* na, const double* nb, int64_t ld, double tau, int64_t* pairs,
+                                 hipStream_t s);
 
 // Multiply: persistent, cost-balanced multiply of the kept pairs into C.
 // pair_scratch holds bdim^3 int32 (each group's packed (tile, k) pairs).

@@ -182,6 +182,7 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
 template <int LEAF, bool VEC, bool NT>
 __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, int64_t n, int64_t bdim) {
     const int m = blockIdx.z;
+    if (job.clear && (blockIdx.x | blockIdx.y | blockIdx.z | threadIdx.x) == 0) *job.clear = 0;
     leaf_sumsq_strip<LEAF, VEC, NT>(job.x[m], n, bdim, blockIdx.y, blockIdx.x, job.sumsq[m], job.norms[m], job.ld);
 }
 
@@ -190,6 +191,7 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_generic_kernel(NormJo
                                                                           int32_t leaf) {
     __shared__ double partial[kNormThreads / 64];
     const int m = blockIdx.z;
+    if (job.clear && (blockIdx.x | blockIdx.y | blockIdx.z | threadIdx.x) == 0) *job.clear = 0;
     const float* __restrict__ x = job.x[m];
     const int64_t ti = blockIdx.y, tj = blockIdx.x;
     const int64_t rows = (ti * leaf + leaf < n ? leaf : n - ti * leaf);

@@ -1,0 +1,166 @@
+// Small products (leaf 32, at most 64 tiles per side): the threshold test of
+// Algorithm 1 and the multiply of the kept pairs in one launch after the leaf
+// norm pass, instead of the pyramid, plan, schedule and multiply launches of
+// the general path.  At these sizes every launch of the general path is a few
+// microseconds of ramp and drain for well under a microsecond of work, and
+// the multiply has too few macro tiles to give every SIMD more than one wave.
+//
+// One workgroup per 2x2 block of output tiles (macro tile (I, J)), sixteen
+// waves:
+//  * wave 0 tests, for every k < bdim, the four products
+//    nA[2I+a][k] * nB[k][2J+b] >= tau (the comparison of the plan kernel, on the
+//    same leaf norms, so the kept pairs are the same; the pyramid only skips
+//    subtrees whose leaf products all fail), compacts the k values kept by any
+//    of the four tiles in ascending order into LDS with their 4-bit membership,
+//    and adds the number of kept pairs to the pair counter;
+//  * waves 4g..4g+3 (k-group g) take the union entries u = g, g+4, g+8, ... and
+//    wave 4g+q computes the product for output tile q = 2a+b of the entries
+//    whose membership has bit q, operands read from global memory (L2) straight
+//    into MFMA operand registers, one entry ahead of the one it multiplies;
+//  * the four k-groups' partial tiles are added in group order through LDS, so
+//    the result does not depend on timing, and group 0 writes C (zero for a
+//    tile with no kept pair).
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace spamm {
+
+namespace {
+constexpr int kSmallLeaf = 32;
+constexpr int kSmallWaves = 16;
+constexpr int kSmallGroups = kSmallWaves / 4;
+}  // namespace
+
+__global__ __launch_bounds__(kSmallWaves * 64, 1) void multiply_small_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ C, int64_t n, int64_t bdim,
+    int64_t mb, const double* __restrict__ na, const double* __restrict__ nb, int64_t ld, double tau,
+    unsigned long long* __restrict__ pairs) {
+    constexpr int L = kSmallLeaf;
+    __shared__ int16_t sk[kSmallMaxBdim];
+    __shared__ uint8_t smem[kSmallMaxBdim];
+    __shared__ int scount;
+    __shared__ float red[kSmallGroups - 1][4][16][64];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = wave >> 2, q = wave & 3, wa = q >> 1, wb = q & 1;
+    const int ir = lane & 31, g = lane >> 5;
+    const int64_t m = blockIdx.x;
+    const int64_t I = m / mb, J = m - (m / mb) * mb;
+
+    if (wave == 0) {
+        const int k = lane;
+        uint32_t mem = 0;
+        if (k < bdim) {
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) {
+                const int64_t ti = 2 * I + (ab >> 1), tj = 2 * J + (ab & 1);
+                if (ti < bdim && tj < bdim) {
+                    const double p = na[ti * ld + k] * nb[int64_t(k) * ld + tj];
+                    if (p >= tau) mem |= 1u << ab;
+                }
+            }
+        }
+        const uint64_t bal = __ballot(mem != 0);
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (mem) {
+            const int pos = __popcll(bal & below);
+            sk[pos] = int16_t(k);
+            smem[pos] = uint8_t(mem);
+        }
+        int cnt = __popc(mem);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane == 0) {
+            scount = __popcll(bal);
+            if (cnt) atomicAdd(pairs, static_cast<unsigned long long>(cnt));
+        }
+    }
+    __syncthreads();
+    const int U = scount;
+
+    // this wave's operands: A rows of output tile row 2I+wa, B columns of tile
+    // column 2J+wb; lane (ir, g) holds k = 16g + s of MFMA step s
+    const int64_t arow = (2 * I + wa) * L + ir, bcol = (2 * J + wb) * L + ir;
+    const bool arow_in = arow < n, bcol_in = bcol < n;
+    const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto load = [&](int u, f4 (&ra)[4], float (&rb)[16]) __attribute__((always_inline)) {
+        const int64_t k0 = int64_t(sk[u]) * L + 16 * g;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = k0 + 4 * v;
+            const bool in = arow_in && col < n;
+            const f4 x = *reinterpret_cast<const f4*>(A + (in ? arow * n + col : 0));
+            ra[v] = in ? x : zero;
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int64_t row = k0 + s;
+            const bool in = bcol_in && row < n;
+            const float x = B[in ? row * n + bcol : 0];
+            rb[s] = in ? x : 0.0f;
+        }
+    };
+    // next entry of this wave's k-group that its tile keeps, or U
+    auto next = [&](int u) __attribute__((always_inline)) {
+        u += kSmallGroups;
+        while (u < U && !((smem[u] >> q) & 1)) u += kSmallGroups;
+        return u;
+    };
+
+    f16v acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    auto mma = [&](const f4 (&ra)[4], const float (&rb)[16]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s >> 2][s & 3], rb[s], acc, 0, 0, 0);
+    };
+
+    f4 ra0[4], ra1[4];
+    float rb0[16], rb1[16];
+    int u = grp;
+    if (u < U && !((smem[u] >> q) & 1)) u = next(u);
+    if (u < U) load(u, ra0, rb0);
+    while (u < U) {
+        const int u1 = next(u);
+        if (u1 < U) load(u1, ra1, rb1);
+        mma(ra0, rb0);
+        if (u1 >= U) break;
+        const int u2 = next(u1);
+        if (u2 < U) load(u2, ra0, rb0);
+        mma(ra1, rb1);
+        u = u2;
+    }
+
+    // partial tiles of groups 1.. through LDS, added in group order
+    if (grp > 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[grp - 1][q][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (grp != 0) return;
+#pragma unroll
+    for (int h = 0; h < kSmallGroups - 1; ++h)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] += red[h][q][r][lane];
+    const int64_t ti = 2 * I + wa, tj = 2 * J + wb;
+    if (ti >= bdim || tj >= bdim || !bcol_in) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = ti * L + 8 * (r >> 2) + 4 * g + (r & 3);
+        if (row < n) C[row * n + bcol] = acc[r];
+    }
+}
+
+hipError_t launch_small_multiply(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                                 const double* na, const double* nb, int64_t ld, double tau, int64_t* pairs,
+                                 hipStream_t s) {
+    if (bdim < 1 || bdim > kSmallMaxBdim || n > bdim * kSmallLeaf || n % 4 != 0) return hipErrorInvalidValue;
+    const int64_t mb = (bdim + 1) / 2;
+    multiply_small_kernel<<<unsigned(mb * mb), kSmallWaves * 64, 0, s>>>(
+        a, b, c, n, bdim, mb, na, nb, ld, tau, reinterpret_cast<unsigned long long*>(pairs));
+    return hipGetLastError();
+}
+
+}  // namespace spamm

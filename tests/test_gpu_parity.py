@@ -350,18 +350,78 @@ def test_runs_are_bitwise_deterministic(c1):
 
 
 def test_staged_calls_equal_the_fused_call(c1):
-    a, b, _, _ = c1
+    """The staged calls (pyramids, plan, execute; prepare, execute) agree
+    bitwise.  The one-call path takes the small-product kernel at this size:
+    the same pairs, and C equal up to the order of the FP32 additions (the
+    k-range of a tile is split between four wave groups)."""
+    a, b, c_ref, _ = c1
     ga, gb = gpu(a), gpu(b)
     c_fused, pairs = sp.multiply(ga, gb, 1e-6, 32)
     pa, pb = sp.pyramid(ga, 32), sp.pyramid(gb, 32)
     offsets, klist, p = sp.plan(pa, pb, 1024, 32, 1e-6)
     c_staged = sp.execute(ga, gb, 32, offsets, klist)
     assert int(p.item()) == pairs
-    assert torch.equal(c_fused, c_staged)
+    rel = float(torch.linalg.norm((c_fused - c_staged).double()) / torch.linalg.norm(c_staged.double()))
+    assert rel <= 1e-6, rel
+    check_c(c_fused.cpu().numpy(), a, b, 1e-6, 32, c_ref=c_ref)
     o2, k2, p2 = sp.prepare(ga, gb, 1e-6, 32)
     assert torch.equal(o2, offsets) and int(p2.item()) == pairs
     assert torch.equal(k2[:pairs], klist[:pairs])
-    assert torch.equal(sp.execute(ga, gb, 32, o2, k2), c_fused)
+    assert torch.equal(sp.execute(ga, gb, 32, o2, k2), c_staged)
+
+
+@pytest.mark.parametrize(
+    "n,q,kind",
+    [
+        (1024, 0.5, "exp"),
+        (1000, 0.7, "rand"),   # ragged last tile row and column
+        (2048, 0.9, "exp"),    # 64 tiles per side: the largest small-product grid
+        (996, 0.0, "rand"),    # tau = 0: every triple
+        (36, 0.3, "rand"),     # 2 x 2 tiles, the second 4 wide
+        (4, 0.0, "rand"),      # one tile of 4 x 4
+        (2052, 0.5, "exp"),    # 65 tiles per side: the general path
+    ],
+)
+def test_small_product_path_matches_oracle_and_staged_path(n, q, kind):
+    """Leaf 32 with at most 64 tiles per side goes through one norm launch and
+    one threshold-and-multiply launch.  Pairs equal the oracle's and the staged
+    path's exactly; C is within the FP32 accumulation bound of the oracle and
+    within 1e-6 (relative Frobenius) of the staged path; every element of C is
+    written; two runs are bitwise equal."""
+    leaf = 32
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.02, 18), inputs.exp_decay(n, 0.02, 19)
+    else:
+        a, b = inputs.uniform_pm1(n, 18), inputs.uniform_pm1(n, 19)
+    prod = oracle_products(a, b, leaf)
+    tau = float(np.quantile(prod, q)) if q > 0 else 0.0
+    c_ref, count, _ = oracle.spamm(a, b, tau, leaf)
+    ga, gb = gpu(a), gpu(b)
+    c = torch.full((n, n), 7.0, device=DEV)
+    pairs_dev = torch.full((1,), 12345, dtype=torch.int64, device=DEV)
+    c, pairs = sp.multiply(ga, gb, tau, leaf, c=c, pairs=pairs_dev)
+    if off_tie(prod, tau).all():
+        assert pairs == count
+    check_c(c.cpu().numpy(), a, b, tau, leaf, c_ref=c_ref)
+    offsets, klist, p = sp.prepare(ga, gb, tau, leaf)
+    assert int(p.item()) == pairs
+    c_staged = sp.execute(ga, gb, leaf, offsets, klist)
+    den = float(torch.linalg.norm(c_staged.double()))
+    diff = float(torch.linalg.norm((c - c_staged).double()))
+    assert diff <= 1e-6 * den + 1e-30, (diff, den)
+    c2, p2 = sp.multiply(ga, gb, tau, leaf)
+    assert p2 == pairs and torch.equal(c2, c)
+
+
+def test_small_product_path_with_nothing_kept():
+    n, leaf = 1024, 32
+    a, b = inputs.uniform_pm1(n, 3), inputs.uniform_pm1(n, 4)
+    ga, gb = gpu(a), gpu(b)
+    for tau in (1e30, math.inf):
+        c = torch.full((n, n), 7.0, device=DEV)
+        _, pairs = sp.multiply(ga, gb, tau, leaf, c=c)
+        assert pairs == 0
+        assert torch.count_nonzero(c).item() == 0
 
 
 @pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 32), (2048, 64), (1100, 64), (1024, 128)])
