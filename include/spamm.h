@@ -133,7 +133,8 @@ spamm_status spamm_execute_scheduled(const float* a, const float* b, int64_t n, 
  * and B (one launch each for both matrices) and the plan for tau, as
  * spamm_pyramid and spamm_plan would produce them.  The pyramids stay in the
  * workspace; offsets, klist and pairs are as in spamm_plan.  Followed by
- * spamm_execute this enqueues exactly the kernels of spamm_multiply.
+ * spamm_execute this enqueues the kernels of spamm_multiply, except for the
+ * small products that spamm_multiply runs in two launches (below).
  * Errors as spamm_plan, plus EINVAL for null a or b. */
 spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau, int32_t leaf, int32_t* offsets,
                            int32_t* klist, int64_t klist_capacity, int64_t* pairs, void* workspace,
@@ -144,6 +145,14 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
  *   c      [n*n] FP32 device output, overwritten.
  *   pairs  one int64 in device memory (may be NULL): number of multiplied
  *          leaf-tile pairs, i.e. the valid ratio of section 3.5.2 times bdim^3.
+ * Small products (leaf 32, at most 64 tiles per side, n a multiple of 4, a and
+ * b 16-byte aligned) take two launches instead: the leaf norm pass, then one
+ * kernel that applies the threshold test of Algorithm 1 to the leaf norms and
+ * multiplies the kept pairs.  The pairs are those of the plan; C differs from
+ * spamm_prepare + spamm_execute only in the order of the FP32 additions (the
+ * k-range of an output tile is split four ways and the parts are added in a
+ * fixed order, so repeated calls agree bitwise); the workspace then holds the
+ * leaf norms but no pyramid or plan.
  * Errors as spamm_pyramid, spamm_plan and spamm_execute. */
 spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double tau, int32_t leaf, float* c,
                             int64_t* pairs, void* workspace, size_t workspace_bytes, void* stream);
