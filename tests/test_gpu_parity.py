@@ -486,3 +486,34 @@ def c1():
 @pytest.fixture(scope="module")
 def alg8192():
     return inputs.workload_alg8192()
+
+
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 64)])
+def test_one_call_graph_replays_equal_eager_run(n, leaf):
+    """spamm_multiply captured in a graph (the small-product path at leaf 32,
+    the general path at leaf 64) and replayed three times with eager work in
+    between: every replay equals the eager call bitwise, C and pairs (the pair
+    counter is cleared by a kernel, not a memset)."""
+    a, b = inputs.exp_decay(n, 0.02, 28), inputs.exp_decay(n, 0.02, 29)
+    ga, gb = gpu(a), gpu(b)
+    ws = sp.workspace(n, leaf, DEV)
+    c = torch.empty((n, n), device=DEV)
+    pairs = torch.empty(1, dtype=torch.int64, device=DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        sp.multiply(ga, gb, 1e-6, leaf, c=c, pairs=pairs, ws=ws, sync=False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    eager_c, eager_pairs = c.clone(), pairs.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sp.multiply(ga, gb, 1e-6, leaf, c=c, pairs=pairs, ws=ws, sync=False)
+    for r in range(3):
+        c.fill_(7.0)
+        pairs.fill_(-5)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(c, eager_c), r
+        assert torch.equal(pairs, eager_pairs), r
