@@ -6,17 +6,17 @@
 // the multiply has too few macro tiles to give every SIMD more than one wave.
 //
 // One workgroup per 2x2 block of output tiles (macro tile (I, J)), sixteen
-// waves:
-//  * wave 0 tests, for every k < bdim, the four products
+// waves in four k-groups of four (wave 4g+q: k-group g, output tile q = 2a+b):
+//  * every wave tests, lane k for every k < bdim, the four products
 //    nA[2I+a][k] * nB[k][2J+b] >= tau (the comparison of the plan kernel, on the
 //    same leaf norms, so the kept pairs are the same; the pyramid only skips
-//    subtrees whose leaf products all fail), compacts the k values kept by any
-//    of the four tiles in ascending order into LDS with their 4-bit membership,
-//    and adds the number of kept pairs to the pair counter;
-//  * waves 4g..4g+3 (k-group g) take the union entries u = g, g+4, g+8, ... and
-//    wave 4g+q computes the product for output tile q = 2a+b of the entries
-//    whose membership has bit q, operands read from global memory (L2) straight
-//    into MFMA operand registers, one entry ahead of the one it multiplies;
+//    subtrees whose leaf products all fail); the k kept by any of the four
+//    tiles, in ascending order, form the union list, and k-group g takes its
+//    entries g, g+4, g+8, ...; wave 0 adds the number of kept pairs to the
+//    pair counter;
+//  * wave 4g+q multiplies the entries of its k-group that tile q keeps, with
+//    operands read from global memory (L2) straight into MFMA operand
+//    registers, the next entry's loads issued before the current entry's MFMAs;
 //  * the four k-groups' partial tiles are added in group order through LDS, so
 //    the result does not depend on timing, and group 0 writes C (zero for a
 //    tile with no kept pair).
@@ -38,9 +38,6 @@ __global__ __launch_bounds__(kSmallWaves * 64, 1) void multiply_small_kernel(
     int64_t mb, const double* __restrict__ na, const double* __restrict__ nb, int64_t ld, double tau,
     unsigned long long* __restrict__ pairs) {
     constexpr int L = kSmallLeaf;
-    __shared__ int16_t sk[kSmallMaxBdim];
-    __shared__ uint8_t smem[kSmallMaxBdim];
-    __shared__ int scount;
     __shared__ float red[kSmallGroups - 1][4][16][64];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -49,44 +46,47 @@ __global__ __launch_bounds__(kSmallWaves * 64, 1) void multiply_small_kernel(
     const int64_t m = blockIdx.x;
     const int64_t I = m / mb, J = m - (m / mb) * mb;
 
-    if (wave == 0) {
+    // Every wave tests lane k's four products itself (the same few norms for
+    // all waves of the block, read from L2), so no barrier separates the test
+    // from the multiply.  u = the position of k in the union k-list; the wave
+    // takes the k its tile keeps whose position is grp modulo the group count.
+    uint64_t todo;
+    {
         const int k = lane;
-        uint32_t mem = 0;
-        if (k < bdim) {
+        const int64_t kc = k < bdim ? k : bdim - 1;
+        double nav[2], nbv[2];
 #pragma unroll
-            for (int ab = 0; ab < 4; ++ab) {
-                const int64_t ti = 2 * I + (ab >> 1), tj = 2 * J + (ab & 1);
-                if (ti < bdim && tj < bdim) {
-                    const double p = na[ti * ld + k] * nb[int64_t(k) * ld + tj];
-                    if (p >= tau) mem |= 1u << ab;
-                }
-            }
+        for (int h = 0; h < 2; ++h) {
+            const int64_t ti = 2 * I + h < bdim ? 2 * I + h : bdim - 1;
+            const int64_t tj = 2 * J + h < bdim ? 2 * J + h : bdim - 1;
+            nav[h] = na[ti * ld + kc];
+            nbv[h] = nb[kc * ld + tj];
+        }
+        uint32_t mem = 0;
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+            const bool in = k < bdim && 2 * I + (ab >> 1) < bdim && 2 * J + (ab & 1) < bdim;
+            if (in && nav[ab >> 1] * nbv[ab & 1] >= tau) mem |= 1u << ab;
         }
         const uint64_t bal = __ballot(mem != 0);
         const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        if (mem) {
-            const int pos = __popcll(bal & below);
-            sk[pos] = int16_t(k);
-            smem[pos] = uint8_t(mem);
-        }
-        int cnt = __popc(mem);
+        const int u = __popcll(bal & below);
+        todo = __ballot(((mem >> q) & 1) && (u % kSmallGroups) == grp);
+        if (wave == 0) {
+            int cnt = __popc(mem);
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (lane == 0) {
-            scount = __popcll(bal);
-            if (cnt) atomicAdd(pairs, static_cast<unsigned long long>(cnt));
+            for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+            if (lane == 0 && cnt) atomicAdd(pairs, static_cast<unsigned long long>(cnt));
         }
     }
-    __syncthreads();
-    const int U = scount;
 
     // this wave's operands: A rows of output tile row 2I+wa, B columns of tile
     // column 2J+wb; lane (ir, g) holds k = 16g + s of MFMA step s
     const int64_t arow = (2 * I + wa) * L + ir, bcol = (2 * J + wb) * L + ir;
     const bool arow_in = arow < n, bcol_in = bcol < n;
     const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    auto load = [&](int u, f4 (&ra)[4], float (&rb)[16]) __attribute__((always_inline)) {
-        const int64_t k0 = int64_t(sk[u]) * L + 16 * g;
+    auto load = [&](int kt, f4 (&ra)[4], float (&rb)[16]) __attribute__((always_inline)) {
+        const int64_t k0 = int64_t(kt) * L + 16 * g;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t col = k0 + 4 * v;
@@ -102,13 +102,6 @@ __global__ __launch_bounds__(kSmallWaves * 64, 1) void multiply_small_kernel(
             rb[s] = in ? x : 0.0f;
         }
     };
-    // next entry of this wave's k-group that its tile keeps, or U
-    auto next = [&](int u) __attribute__((always_inline)) {
-        u += kSmallGroups;
-        while (u < U && !((smem[u] >> q) & 1)) u += kSmallGroups;
-        return u;
-    };
-
     f16v acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
@@ -119,18 +112,24 @@ __global__ __launch_bounds__(kSmallWaves * 64, 1) void multiply_small_kernel(
 
     f4 ra0[4], ra1[4];
     float rb0[16], rb1[16];
-    int u = grp;
-    if (u < U && !((smem[u] >> q) & 1)) u = next(u);
-    if (u < U) load(u, ra0, rb0);
-    while (u < U) {
-        const int u1 = next(u);
-        if (u1 < U) load(u1, ra1, rb1);
-        mma(ra0, rb0);
-        if (u1 >= U) break;
-        const int u2 = next(u1);
-        if (u2 < U) load(u2, ra0, rb0);
-        mma(ra1, rb1);
-        u = u2;
+    // the wave's k values in ascending order (bits of todo), one ahead
+    auto pop = [&]() __attribute__((always_inline)) {
+        const int kt = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        return kt;
+    };
+    if (todo) {
+        load(pop(), ra0, rb0);
+        while (true) {
+            const bool more1 = todo != 0;
+            if (more1) load(pop(), ra1, rb1);
+            mma(ra0, rb0);
+            if (!more1) break;
+            const bool more2 = todo != 0;
+            if (more2) load(pop(), ra0, rb0);
+            mma(ra1, rb1);
+            if (!more2) break;
+        }
     }
 
     // partial tiles of groups 1.. through LDS, added in group order
