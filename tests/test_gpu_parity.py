@@ -517,3 +517,21 @@ def test_one_call_graph_replays_equal_eager_run(n, leaf):
         torch.cuda.synchronize()
         assert torch.equal(c, eager_c), r
         assert torch.equal(pairs, eager_pairs), r
+
+
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 64)])
+def test_one_call_without_a_pair_counter(n, leaf):
+    """spamm_multiply with pairs = NULL counts into the workspace instead (the
+    small-product path clears that slot in its norm pass): C equals the call
+    that returns the count, bitwise, on repeated calls."""
+    a, b = inputs.exp_decay(n, 0.02, 38), inputs.exp_decay(n, 0.02, 39)
+    ga, gb = gpu(a), gpu(b)
+    ws = sp.workspace(n, leaf, DEV)
+    c_ref, _ = sp.multiply(ga, gb, 1e-6, leaf, ws=ws)
+    for _ in range(2):
+        c = torch.full((n, n), 7.0, device=DEV)
+        st = sp._lib.spamm_multiply(sp._ptr(ga), sp._ptr(gb), n, 1e-6, leaf, sp._ptr(c), None, sp._ptr(ws),
+                                    ws.numel(), sp._stream(DEV))
+        assert st == 0
+        torch.cuda.synchronize()
+        assert torch.equal(c, c_ref)
