@@ -543,6 +543,7 @@ def cpu_baseline_batch(a_l, b_l, leaves, tau, specs, budget_s):
     is spent; the rate is their dense-equivalent flops over the time."""
     import oracle
 
+    oracle.use_native_build()  # -O3 -march=native, compiled on this host
     order = np.random.default_rng(77).permutation(len(specs))
     done, flop, t_all = 0, 0.0, 0.0
     for q in order:
@@ -579,10 +580,11 @@ def cpu_baseline(a_np, b_np, c_gpu, tau, leaf, budget_s):
     Also compares the GPU result with the oracle on the tiles of that pass."""
     import oracle
 
+    build = oracle.use_native_build()  # -O3 -march=native, compiled on this host
     n = a_np.shape[0]
     bd = oracle.bdim(n, leaf)
     total = bd * bd
-    log(f"cpu baseline: oracle on {oracle.max_threads()} threads, budget {budget_s:.0f}s")
+    log(f"cpu baseline: oracle ({build.name}) on {oracle.max_threads()} threads, budget {budget_s:.0f}s")
     order = np.random.default_rng(1234).permutation(total)
     chunk = 256
     times, num, den = [], 0.0, 0.0
@@ -625,7 +627,7 @@ def cpu_baseline(a_np, b_np, c_gpu, tau, leaf, budget_s):
     log(f"cpu baseline: {sample}")
     return (
         {"value": value, "unit": "TFLOP/s (dense-equivalent 2N^3/t)", "cores": oracle.max_threads(),
-         "kind": "oracle", "cpu": host_cpu(), "sample": sample},
+         "kind": "oracle", "cpu": host_cpu(), "build": "gcc -O3 -march=native -fopenmp", "sample": sample},
         rel,
     )
 

@@ -17,7 +17,9 @@ from pathlib import Path
 import numpy as np
 
 _HERE = Path(__file__).resolve().parent
-LIB_PATH = _HERE / "libspamm_oracle.so"
+# SPAMM_ORACLE_LIB selects another build of the same source (the sanitizer
+# variant of oracle/build.py, for running the pin tests under ASan/UBSan)
+LIB_PATH = Path(os.environ.get("SPAMM_ORACLE_LIB", _HERE / "libspamm_oracle.so"))
 _lib = None
 
 
@@ -29,7 +31,25 @@ def _load():
         from . import build as _build
 
         _build.build_oracle()
-    lib = ctypes.CDLL(str(LIB_PATH))
+    return _bind(ctypes.CDLL(str(LIB_PATH)))
+
+
+def use_native_build() -> Path:
+    """Switch to the -O3 -march=native build of the oracle, compiled now on the
+    host that runs it (a build from another host may use instructions this one
+    lacks): for timing it as a CPU baseline.  The arithmetic is the same C
+    source with the same FP flags."""
+    global _lib
+    from . import build as _build
+
+    path = _build.build_oracle(native=True)
+    _lib = None
+    _lib = _bind(ctypes.CDLL(str(path)))
+    return path
+
+
+def _bind(lib):
+    global _lib
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     vp = ctypes.c_void_p
     lib.oracle_bdim.argtypes = [i64, i32]
