@@ -5,11 +5,12 @@ Default workload: algebraic-decay matrices A_ij = s_ij / (1 + |i-j|)^2 with
 random signs (A seed 0, B seed 1), N = 8192, FP32, leaf tiles of 64, tau = 1e-6.
 
 One step = one pass of the whole hot path over the resident inputs:
-spamm_prepare (leaf norms and pyramids of A and B, plan for tau), then
-spamm_execute as its two launch steps, spamm_schedule (the multiply schedule)
-and spamm_execute_scheduled (the MFMA multiply kernel of the kept pairs).  HIP
-events on the stream the library launches on bracket every step and each
-stage inside it; the roofline figure uses the multiply kernel's own time.
+spamm_prepare_schedule (leaf norms and pyramids of A and B, then the plan for
+tau and the multiply schedule from one launch), then spamm_execute_scheduled
+(the MFMA multiply kernel of the kept pairs).  (Reduced precision: the staged
+calls spamm_prepare*, spamm_schedule, the multiply.)  HIP events on the stream
+the library launches on bracket every step and each stage inside it; the
+roofline figure uses the multiply kernel's own time.
 
   --write-traffic FETCH_CSV WRITE_CSV  turns two rocprofv3 --pmc runs of this
   script into profiles/multiply_traffic.json (HBM bytes per multiply launch).
@@ -115,17 +116,22 @@ def parse_args():
     return ap.parse_args()
 
 
+def traffic_records() -> list[dict]:
+    try:
+        data = json.loads(TRAFFIC_FILE.read_text())
+    except (OSError, ValueError):
+        return []
+    return data.get("records", []) if isinstance(data, dict) else []
+
+
 def traffic_entry(kernel: str, sources: list[Path], workload: str):
     """HBM bytes per multiply launch from the committed counter summary, if it
     was taken on this kernel, its current sources and this workload (else None)."""
-    try:
-        rec = json.loads(TRAFFIC_FILE.read_text())
-    except (OSError, ValueError):
-        return None
-    if rec.get("source_sha256") != sources_sha256(sources) or rec.get("kernel") != kernel \
-            or rec.get("workload") != workload:
-        return None
-    return rec
+    sha = sources_sha256(sources)
+    for rec in traffic_records():
+        if rec.get("source_sha256") == sha and rec.get("kernel") == kernel and rec.get("workload") == workload:
+            return rec
+    return None
 
 
 def _counter_rows(path: str, counter: str):
@@ -137,13 +143,24 @@ def _counter_rows(path: str, counter: str):
                 yield row["Kernel_Name"], float(row["Counter_Value"])
 
 
-def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float, commands: list[str]) -> int:
+def write_traffic(fetch_csv: str, write_csv: str, args, commands: list[str]) -> int:
     """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE)
-    into profiles/multiply_traffic.json: per-dispatch KiB of the multiply launch
-    (the sum over its kernels), each scaled by what the same counter reads for
-    the CALIB_BYTES device copy.  (Default workload and precision only.)"""
-    kernel, sources = multiply_kernel(n, leaf)
-    out = {"kernel": kernel, "workload": workload_name(n, leaf, tau),
+    into a record of profiles/multiply_traffic.json: per-dispatch KiB of the
+    multiply launch (the sum over its kernels), each scaled by what the same
+    counter reads for the CALIB_BYTES device copy.  The record is keyed by the
+    kernel, the workload (the same arguments as the profiled runs) and the
+    kernel's sources; it replaces an older record of the same kernel and
+    workload."""
+    n, leaf, prec = args.n, args.leaf, args.precision
+    workload = workload_name(n, leaf, args.tau, args.workload, args.alpha, prec)
+    names = {name for name, _ in _counter_rows(fetch_csv, "FETCH_SIZE")}
+    options = [multiply_kernel(n, leaf, prec, st) for st in ((False, True) if prec != "fp32" else (False,))]
+    found = [(k, src) for k, src in options if all(any(part in nm for nm in names) for part in k.split(" + "))]
+    if not found:
+        print(f"{fetch_csv}: no rows of {[k for k, _ in options]}", file=sys.stderr)
+        return 1
+    kernel, sources = found[0]
+    out = {"kernel": kernel, "workload": workload,
            "sources": [str(src.relative_to(ROOT)) for src in sources],
            "source_sha256": sources_sha256(sources), "commands": commands}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -162,7 +179,8 @@ def write_traffic(fetch_csv: str, write_csv: str, n: int, leaf: int, tau: float,
         out[f"{key}_scale"] = scale
     out["hbm_bytes_per_launch"] = round(1024.0 * (out["fetch_kib_per_dispatch"] * out["fetch_scale"]
                                                   + out["write_kib_per_dispatch"] * out["write_scale"]))
-    TRAFFIC_FILE.write_text(json.dumps(out, indent=1) + "\n")
+    recs = [r for r in traffic_records() if (r.get("kernel"), r.get("workload")) != (kernel, workload)]
+    TRAFFIC_FILE.write_text(json.dumps({"records": recs + [out]}, indent=1) + "\n")
     print(json.dumps(out, indent=1))
     return 0
 
@@ -182,7 +200,7 @@ def workload_name(n: int, leaf: int, tau: float, kind: str = "alg", alpha: float
 def main() -> int:
     args = parse_args()
     if args.write_traffic:
-        return write_traffic(*args.write_traffic, args.n, args.leaf, args.tau, args.traffic_command)
+        return write_traffic(*args.write_traffic, args, args.traffic_command)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(
@@ -262,8 +280,14 @@ def main() -> int:
         if staged:
             split_buf = sp.split_buffer(n, prec, dev)
 
+    # FP32: the first stage is spamm_prepare_schedule (norms, pyramids, then
+    # the plan and the multiply schedule from one launch), so no schedule stage
+    fused_plan = prec == "fp32"
+
     def stage_prepare(t):
-        if prec == "fp32" or (prec == "bf16" and not staged):
+        if fused_plan:
+            return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws, schedule=True)
+        if prec == "bf16" and not staged:
             return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
         if prec == "f16x3" and not staged:
             return sp.prepare_scales(a, b, t, leaf, header, bufs=bufs, ws=ws)
@@ -286,7 +310,8 @@ def main() -> int:
             sp.multiply(a, b, t, leaf, c=c, pairs=bufs[2], ws=ws, sync=False)
             return
         offsets, klist, _ = stage_prepare(t)
-        sp.schedule(offsets, klist, n, leaf, ws=ws)
+        if not fused_plan:
+            sp.schedule(offsets, klist, n, leaf, ws=ws)
         stage_multiply(offsets, klist)
 
     def timed(t, steps, warmup):
@@ -309,7 +334,8 @@ def main() -> int:
             e[0].record()
             offsets, klist, _ = stage_prepare(t)
             e[1].record()
-            sp.schedule(offsets, klist, n, leaf, ws=ws)
+            if not fused_plan:
+                sp.schedule(offsets, klist, n, leaf, ws=ws)
             e[2].record()
             stage_multiply(offsets, klist)
             e[3].record()
@@ -360,6 +386,8 @@ def main() -> int:
         },
         "stages_ms": {"prepare": round(prep_ms, 4), "schedule": round(sched_ms, 4), "multiply": round(kern_ms, 4)},
     }
+    if fused_plan:  # spamm_prepare_schedule: the schedule comes with the plan
+        result["stages_ms"] = {"prepare_schedule": round(prep_ms, 4), "multiply": round(kern_ms, 4)}
     if one_call:
         result["stages_ms"] = {"spamm_multiply": round(ms_step, 4)}
         result["config"]["entry"] = "spamm_multiply"
@@ -458,7 +486,8 @@ def run_batch(args, torch, sp, inputs, dev) -> int:
             if args.retune:
                 autotune.save(table, args.retune)
         tune_s = time.perf_counter() - t0
-        leaves = [autotune.choose(table, n, math.sqrt(aa * ab)) for n, aa, ab, _, _ in specs]
+        leaves = [autotune.choose(table, n, autotune.density(a, b, tau))
+                  for (n, *_), a, b in zip(specs, a_l, b_l)]
     bt = sp.Batch(a_l, b_l, leaves, [tau] * len(specs))
     dense_flop = sum(2.0 * n**3 for n, *_ in specs)
 
@@ -519,6 +548,8 @@ def run_batch(args, torch, sp, inputs, dev) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch of {len(specs)} products, n log-uniform in [256, 4096], exponential decay "
                                f"rates U[0.01, 0.5), tau={tau:g}, autotuned leaves",
+                   "form": "each stage one launch over the whole batch (about 11 launches, one persistent multiply "
+                           "per leaf class) captured in one graph and replayed; not one persistent launch",
                    "products": len(specs), "tau": tau, "leaves": hist, "pairs": int(sum(pairs)),
                    "dense_equiv_flop": dense_flop},
         "stages_ms": {"per_product_loop": round(loop_ms, 4), "batched_eager": round(eager_ms, 4),

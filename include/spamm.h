@@ -17,10 +17,17 @@
  *  - stream is a hipStream_t (NULL: the default stream).  Every call only
  *    enqueues work on that stream and returns; nothing synchronises the host.
  *    Outputs are valid once the stream reaches that point.
- *  - The library allocates no memory: callers pass every output buffer and a
- *    workspace of at least spamm_workspace_bytes(N, leaf) bytes.  The library
- *    never frees or retains caller memory.  Calls that share a workspace must
- *    be ordered (same stream, or synchronised).
+ *  - Callers pass every output buffer.  The workspace is either the caller's
+ *    (at least spamm_workspace_bytes(N, leaf) bytes of device memory; the
+ *    library then allocates nothing) or NULL: the library then uses one
+ *    workspace per device that it allocates on first use, grows when a call
+ *    needs more (after synchronising the device, so the first call at a new
+ *    largest size must not be under graph capture), and frees in
+ *    spamm_release(); workspace_bytes is ignored.  The library never frees or
+ *    retains caller memory.  Calls that share a workspace, including the
+ *    cached one of a device, must be ordered (same stream, or synchronised),
+ *    and a pair of calls that passes state through it (spamm_prepare, then
+ *    spamm_execute) must not be separated by a call that grows it.
  *  - Errors: argument checks happen on the host before anything is enqueued;
  *    on a failure nothing is written and a status code is returned.
  *    SPAMM_EDEVICE reports a failed HIP call; spamm_last_error() gives the
@@ -39,7 +46,8 @@ extern "C" {
 typedef enum spamm_status {
     SPAMM_OK = 0,
     SPAMM_EINVAL = 1,       /* invalid argument: size, pointer, tau, aliasing */
-    SPAMM_ENOSPACE = 2,     /* workspace or output capacity too small */
+    SPAMM_ENOSPACE = 2,     /* workspace or output capacity too small, or the cached
+                               workspace could not be allocated */
     SPAMM_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
     SPAMM_EUNSUPPORTED = 4  /* leaf size or problem size not handled by the GPU path */
 } spamm_status;
@@ -57,8 +65,15 @@ int32_t spamm_levels(int64_t n, int32_t leaf);
 /* Number of FP64 entries of a norm pyramid: sum over l = 0..Lv of 4^l.  Host only. */
 int64_t spamm_pyramid_size(int64_t n, int32_t leaf);
 
-/* 1 when the GPU path has kernels for this leaf size (32, 64, 128), else 0. */
+/* 1 when the GPU path has multiply kernels for this leaf size (LoNum of
+ * section 3: 16, 32, 64, 128), else 0. */
 int32_t spamm_leaf_supported(int32_t leaf);
+
+/* Free the workspaces the library allocated for calls with a NULL workspace
+ * (one per device that ran such a call), after synchronising each of those
+ * devices.  Later calls with a NULL workspace allocate again.  Host only;
+ * SPAMM_EDEVICE when a HIP call fails. */
+spamm_status spamm_release(void);
 
 /* Workspace size that every entry point below accepts for (n, leaf); 0 when the
  * arguments are invalid.  Host only. */
@@ -139,6 +154,18 @@ spamm_status spamm_execute_scheduled(const float* a, const float* b, int64_t n, 
 spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau, int32_t leaf, int32_t* offsets,
                            int32_t* klist, int64_t klist_capacity, int64_t* pairs, void* workspace,
                            size_t workspace_bytes, void* stream);
+
+/* spamm_prepare followed by spamm_schedule on the plan it writes (the first
+ * half of spamm_multiply): the same offsets, klist, pairs and workspace
+ * contents, so spamm_execute_scheduled may follow.  For leaf 32 and 64 the
+ * plan and the multiply schedule come from one launch (the norm tests,
+ * bitmaps, map_offset and validNum of Algorithm 2 and the union k-lists of
+ * section 3.5.1's work split, with the prefix over tile rows by a
+ * single-pass look-back) instead of six.  Errors as spamm_prepare and
+ * spamm_schedule. */
+spamm_status spamm_prepare_schedule(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                    int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs,
+                                    void* workspace, size_t workspace_bytes, void* stream);
 
 /* The whole SpAMM hot path: pyramids of A and B, the plan for tau, and the
  * multiplication of the kept pairs, enqueued back to back on one stream.

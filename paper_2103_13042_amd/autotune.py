@@ -5,13 +5,17 @@ tested and kept), so the tuner does not change a product behind the caller's
 back: it proposes a leaf per product from measured speed, the caller adopts it
 as part of the problem, and results are checked at the chosen leaf.
 
-``tune`` times the whole single-product path (spamm_multiply) for each
-candidate leaf on one exponential-decay pair per (size, decay-rate) bucket; a
-bucket keeps the default leaf unless another is faster by more than
-``MARGIN`` (so timing noise does not flip the choice).  ``choose`` maps a
-product to the nearest bucket in (log n, log alpha).  The table of the last
-tuning run is kept in ``data/leaf_table.json`` so that the same batch gets the
-same leaves from run to run.
+``tune`` times the batched path itself (spamm_batch_run, every stage) for
+each candidate leaf on a batch of copies of one exponential-decay pair per
+(size, decay-rate) bucket; a bucket keeps the default leaf unless another is
+faster by more than ``MARGIN`` (so timing noise does not flip the choice).
+Buckets are keyed on what the library measures of a product, not on how it
+was generated: its size and its density, the fraction of leaf-32 tile
+triples the plan keeps at the product's tau (``density``: norm pass, pyramid
+and plan at leaf 32, pairs / bdim^3).  ``choose`` maps a product to the
+nearest bucket in (log n, log density).  The table of the last tuning run is
+kept in ``data/leaf_table.json`` so that the same batch gets the same leaves
+from run to run.
 """
 
 from __future__ import annotations
@@ -31,6 +35,8 @@ ALPHAS = (0.01, 0.05, 0.2, 0.5)
 LEAVES = (32, 64, 128)
 DEFAULT_LEAF = 64
 MARGIN = 0.10
+PROBE_LEAF = 32  # the leaf at which a product's density is measured
+COPIES = 8       # products per timed batch
 TABLE_FILE = Path(__file__).resolve().parent / "data" / "leaf_table.json"
 
 
@@ -47,30 +53,40 @@ def _time_ms(fn, reps: int) -> float:
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
 
 
+def density(a: torch.Tensor, b: torch.Tensor, tau: float) -> float:
+    """Fraction of the leaf-32 tile triples of (a, b) whose norm product is at
+    least tau (the plan's kept pairs / bdim^3), at least one triple."""
+    n = a.shape[0]
+    _, _, pairs = sp.prepare(a, b, tau, PROBE_LEAF)
+    return max(int(pairs.item()), 1) / float(sp.bdim(n, PROBE_LEAF)) ** 3
+
+
 def tune(device, *, tau: float = 1e-6, sizes=SIZES, alphas=ALPHAS, leaves=LEAVES, reps: int = 9) -> dict:
-    """{"buckets": [{"n", "alpha", "ms": {leaf: ms}, "leaf"}], ...}"""
+    """{"buckets": [{"n", "alpha", "density", "ms": {leaf: ms per product}, "leaf"}], ...}"""
     rows = []
     for n in sizes:
         for al in alphas:
             a = inputs.exp_decay_torch(n, al, 900, device)
             b = inputs.exp_decay_torch(n, al, 901, device)
-            c = torch.empty_like(a)
             ms = {}
             for leaf in leaves:
-                ws = sp.workspace(n, leaf, device)
-                pairs = torch.empty(1, dtype=torch.int64, device=device)
-                ms[leaf] = _time_ms(lambda: sp.multiply(a, b, tau, leaf, c=c, pairs=pairs, ws=ws, sync=False), reps)
+                bt = sp.Batch([a] * COPIES, [b] * COPIES, [leaf] * COPIES, [tau] * COPIES)
+                ms[leaf] = _time_ms(bt.run, reps) / COPIES
+                del bt
             best = min(ms, key=ms.get)
             if DEFAULT_LEAF in ms and ms[best] > (1.0 - MARGIN) * ms[DEFAULT_LEAF]:
                 best = DEFAULT_LEAF
-            rows.append({"n": n, "alpha": al, "ms": {str(k): v for k, v in ms.items()}, "leaf": int(best)})
-    return {"tau": tau, "leaves": list(leaves), "margin": MARGIN, "default": DEFAULT_LEAF, "buckets": rows}
+            rows.append({"n": n, "alpha": al, "density": density(a, b, tau), "ms": {str(k): v for k, v in ms.items()},
+                         "leaf": int(best)})
+    return {"tau": tau, "leaves": list(leaves), "margin": MARGIN, "default": DEFAULT_LEAF, "probe_leaf": PROBE_LEAF,
+            "copies": COPIES, "buckets": rows}
 
 
-def choose(table: dict, n: int, alpha: float) -> int:
+def choose(table: dict, n: int, dens: float) -> int:
+    """The leaf of the bucket nearest to (n, density) in (log n, log density)."""
     best, dist = None, math.inf
     for r in table["buckets"]:
-        d = (math.log(n / r["n"])) ** 2 + (math.log(alpha / r["alpha"])) ** 2
+        d = (math.log(n / r["n"])) ** 2 + (math.log(dens / r["density"])) ** 2
         if d < dist:
             best, dist = r["leaf"], d
     return int(best)

@@ -31,6 +31,7 @@ _SIGS = {
     "spamm_levels": (_i32, [_i64, _i32]),
     "spamm_pyramid_size": (_i64, [_i64, _i32]),
     "spamm_leaf_supported": (_i32, [_i32]),
+    "spamm_release": (_st, []),
     "spamm_workspace_bytes": (_sz, [_i64, _i32]),
     "spamm_norms": (_st, [_vp, _i64, _i32, _vp, _vp]),
     "spamm_pyramid": (_st, [_vp, _i64, _i32, _vp, _vp, _sz, _vp]),
@@ -40,6 +41,7 @@ _SIGS = {
     "spamm_execute_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "spamm_multiply": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "spamm_prepare_schedule": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
     "spamm_search_valid_ratio": (_st, [_vp, _vp, _i64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_mlp_param_count": (_i64, []),
     "spamm_mlp_acts_floats": (_i64, [_i32]),
@@ -115,6 +117,16 @@ def leaf_supported(leaf: int) -> bool:
 
 def workspace_bytes(n: int, leaf: int) -> int:
     return int(_lib.spamm_workspace_bytes(n, leaf))
+
+
+def release() -> None:
+    """Free the library's cached per-device workspaces (spamm_release)."""
+    _check(_lib.spamm_release(), "spamm_release")
+
+
+# passed as ws= to multiply(): the library's own cached workspace of the device
+# (a NULL workspace pointer at the C ABI)
+LIBRARY_WORKSPACE = "library"
 
 
 # -- marshalling helpers ----------------------------------------------------
@@ -211,19 +223,22 @@ def plan_buffers(n: int, leaf: int, device: torch.device):
     )
 
 
-def prepare(a, b, tau: float, leaf: int, *, bufs=None, ws=None):
-    """Norms, pyramids and plan of A and B (spamm_prepare): (offsets, klist, pairs)."""
+def prepare(a, b, tau: float, leaf: int, *, bufs=None, ws=None, schedule: bool = False):
+    """Norms, pyramids and plan of A and B (spamm_prepare; with schedule=True
+    also the multiply schedule, spamm_prepare_schedule): (offsets, klist, pairs)."""
     n = _square_f32(a, "a")
     if _square_f32(b, "b") != n:
         raise ValueError("a and b must have the same size")
     offsets, klist, pairs = plan_buffers(n, leaf, a.device) if bufs is None else bufs
     ws = workspace(n, leaf, a.device) if ws is None else ws
+    fn, name = ((_lib.spamm_prepare_schedule, "spamm_prepare_schedule") if schedule
+                else (_lib.spamm_prepare, "spamm_prepare"))
     _check(
-        _lib.spamm_prepare(
+        fn(
             _ptr(a), _ptr(b), n, float(tau), leaf, _ptr(offsets), _ptr(klist), klist.numel(), _ptr(pairs),
             _ptr(ws), ws.numel(), _stream(a.device),
         ),
-        "spamm_prepare",
+        name,
     )
     return offsets, klist, pairs
 
@@ -289,10 +304,14 @@ def multiply(a, b, tau: float, leaf: int, *, c=None, pairs=None, ws=None, sync: 
     c = torch.empty_like(a) if c is None else c
     _square_f32(c, "c")
     pairs = torch.empty(1, dtype=torch.int64, device=a.device) if pairs is None else pairs
-    ws = workspace(n, leaf, a.device) if ws is None else ws
+    if isinstance(ws, str) and ws == LIBRARY_WORKSPACE:
+        ws_ptr, ws_bytes = None, 0
+    else:
+        ws = workspace(n, leaf, a.device) if ws is None else ws
+        ws_ptr, ws_bytes = _ptr(ws), ws.numel()
     _check(
         _lib.spamm_multiply(
-            _ptr(a), _ptr(b), n, float(tau), leaf, _ptr(c), _ptr(pairs), _ptr(ws), ws.numel(), _stream(a.device)
+            _ptr(a), _ptr(b), n, float(tau), leaf, _ptr(c), _ptr(pairs), ws_ptr, ws_bytes, _stream(a.device)
         ),
         "spamm_multiply",
     )

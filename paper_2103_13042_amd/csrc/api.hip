@@ -88,6 +88,7 @@ Layout make_layout(const Geom& g) {
         macros < size_t(spamm::kSplitMaxGroups) ? (macros + 7) / 8 * 8 : size_t(spamm::kSplitMaxGroups);
     L.fix_slot_bytes = dma ? sizeof(float) * groups * 2 * spamm::kSplitSlotFloats : 0;
     L.fix_slots = take(L.fix_slot_bytes);
+    L.pm_state = take(sizeof(int64_t) * size_t(spamm::plan_macro_clear_words(g.bdim)));
     L.pairs = take(sizeof(int64_t));
     L.scalars = take(4 * sizeof(double));
     L.partials = take(sizeof(double) * 1024);
@@ -124,9 +125,66 @@ spamm_status check_grid(const Geom& g) {
     return SPAMM_OK;
 }
 
-spamm_status check_workspace(const Geom& g, void* ws, size_t bytes) {
-    if (!ws) return fail(SPAMM_EINVAL, "workspace is null");
+// Workspaces the library keeps for callers that pass none: one per device,
+// grown to the largest size asked for, freed by spamm_release.
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_cache_mu;
+void* g_cache_ptr[kMaxDevices] = {};
+size_t g_cache_bytes[kMaxDevices] = {};
+}  // namespace
+
+spamm_status cached_workspace(size_t need, void** ws, size_t* bytes) {
+    int dev = 0;
+    spamm_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st != SPAMM_OK) return st;
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPAMM_EUNSUPPORTED, "device %d beyond the workspace cache", dev);
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (g_cache_bytes[dev] < need) {
+        if (g_cache_ptr[dev]) {
+            // the old buffer may still be in use by enqueued work
+            if ((st = hip_check(hipDeviceSynchronize(), "synchronize before growing the cached workspace")) !=
+                SPAMM_OK)
+                return st;
+            if ((st = hip_check(hipFree(g_cache_ptr[dev]), "hipFree of the cached workspace")) != SPAMM_OK)
+                return st;
+            g_cache_ptr[dev] = nullptr;
+            g_cache_bytes[dev] = 0;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(SPAMM_ENOSPACE, "cannot allocate a cached workspace of %zu bytes on device %d", need, dev);
+        }
+        g_cache_ptr[dev] = p;
+        g_cache_bytes[dev] = need;
+    }
+    *ws = g_cache_ptr[dev];
+    *bytes = g_cache_bytes[dev];
+    return SPAMM_OK;
+}
+
+spamm_status release_cached_workspaces() {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    int cur = 0;
+    spamm_status st = hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (st != SPAMM_OK) return st;
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (!g_cache_ptr[d]) continue;
+        if ((st = hip_check(hipSetDevice(d), "hipSetDevice")) != SPAMM_OK) break;
+        if ((st = hip_check(hipDeviceSynchronize(), "synchronize before releasing the cached workspace")) != SPAMM_OK)
+            break;
+        if ((st = hip_check(hipFree(g_cache_ptr[d]), "hipFree of the cached workspace")) != SPAMM_OK) break;
+        g_cache_ptr[d] = nullptr;
+        g_cache_bytes[d] = 0;
+    }
+    const spamm_status st2 = hip_check(hipSetDevice(cur), "hipSetDevice");
+    return st != SPAMM_OK ? st : st2;
+}
+
+spamm_status check_workspace(const Geom& g, void*& ws, size_t& bytes) {
     const size_t need = make_layout(g).total;
+    if (!ws) return cached_workspace(need, &ws, &bytes);
     if (bytes < need)
         return fail(SPAMM_ENOSPACE, "workspace of %zu bytes, %zu needed", bytes, need);
     return SPAMM_OK;
@@ -138,12 +196,14 @@ spamm_status check_tau(double tau) {
 }
 
 spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
-                              hipStream_t s) {
+                              hipStream_t s, int64_t* clear, int64_t clear_count) {
     const Layout L = make_layout(g);
     const int64_t leaf_level = spamm::level_offset(g.lv);
     spamm::NormJob nj{};
     spamm::PyramidJob pj{};
     nj.ld = g.side;  // the norm pass writes the padded leaf level of both pyramids
+    nj.clear = clear;
+    nj.clear_count = clear_count;
     bool vec = (g.n % 4) == 0;
     for (int m = 0; m < nmat; ++m) {
         nj.x[m] = x[m];
@@ -174,13 +234,42 @@ spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, dou
     return hip_check(spamm::launch_plan_fill(masks, counts, boffs, g.bdim, offsets, klist, s), "plan fill kernel");
 }
 
+spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, double tau, int32_t* offsets,
+                             int32_t* klist, int64_t* pairs, void* ws, hipStream_t s, bool schedule) {
+    const Layout L = make_layout(g);
+    double* pa = at<double>(ws, L.pyr[0]);
+    double* pb = at<double>(ws, L.pyr[1]);
+    const float* xs[2] = {a, b};
+    double* ps[2] = {pa, pb};
+    const bool fused = schedule && (g.leaf == 32 || g.leaf == 64);
+    int64_t* state = at<int64_t>(ws, L.pm_state);
+    spamm_status st = enqueue_pyramids(g, xs, 2, ps, ws, s, fused ? state : nullptr,
+                                       fused ? spamm::plan_macro_clear_words(g.bdim) : 0);
+    if (st != SPAMM_OK) return st;
+    if (!fused) {
+        if ((st = enqueue_plan(g, pa, pb, tau, false, offsets, klist, pairs, ws, s)) != SPAMM_OK) return st;
+        return schedule ? enqueue_schedule(g, offsets, klist, ws, s) : SPAMM_OK;
+    }
+    const spamm::MacroSchedule ms = macro_schedule(L, ws);
+    spamm::PlanMacroOut o{};
+    o.masks = at<uint64_t>(ws, L.masks);
+    o.offsets = offsets;
+    o.klist = klist;
+    o.pairs = pairs;
+    o.uprefix = ms.uprefix;
+    o.items = ms.items;
+    o.flags = reinterpret_cast<unsigned long long*>(state);
+    o.ticket = reinterpret_cast<unsigned int*>(state + (g.bdim + 1) / 2);
+    return hip_check(spamm::launch_plan_macro(pa, pb, g.bdim, g.lv, tau, o, s), "plan and schedule kernel");
+}
+
 spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const float* c) {
     if (!a || !b || !c) return fail(SPAMM_EINVAL, "null matrix pointer");
     const size_t bytes = sizeof(float) * size_t(g.n) * size_t(g.n);
     if (overlaps(c, bytes, a, bytes) || overlaps(c, bytes, b, bytes))
         return fail(SPAMM_EINVAL, "C overlaps A or B");
     if (!spamm_leaf_supported(g.leaf))
-        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (32, 64, 128)", g.leaf);
+        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (16, 32, 64, 128)", g.leaf);
     return SPAMM_OK;
 }
 
@@ -300,7 +389,12 @@ int64_t spamm_pyramid_size(int64_t n, int32_t leaf) {
     return make_geom(n, leaf, &g) ? g.pyr : 0;
 }
 
-int32_t spamm_leaf_supported(int32_t leaf) { return (leaf == 32 || leaf == 64 || leaf == 128) ? 1 : 0; }
+int32_t spamm_leaf_supported(int32_t leaf) { return (leaf == 16 || leaf == 32 || leaf == 64 || leaf == 128) ? 1 : 0; }
+
+spamm_status spamm_release(void) {
+    g_last_error[0] = '\0';
+    return release_cached_workspaces();
+}
 
 size_t spamm_workspace_bytes(int64_t n, int32_t leaf) {
     Geom g;
@@ -374,7 +468,7 @@ spamm_status spamm_schedule(const int32_t* offsets, const int32_t* klist, int64_
     if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
     if (!offsets || !klist) return fail(SPAMM_EINVAL, "null plan pointer");
     if (!spamm_leaf_supported(leaf))
-        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (32, 64, 128)", leaf);
+        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (16, 32, 64, 128)", leaf);
     spamm_status st = check_grid(g);
     if (st != SPAMM_OK) return st;
     if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
@@ -409,14 +503,26 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
     if (klist_capacity < g.ntiles * g.bdim)
         return fail(SPAMM_ENOSPACE, "klist capacity %lld < bdim^3 = %lld", (long long)klist_capacity,
                     (long long)(g.ntiles * g.bdim));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = make_layout(g);
-    double* pa = at<double>(workspace, L.pyr[0]);
-    double* pb = at<double>(workspace, L.pyr[1]);
-    const float* xs[2] = {a, b};
-    double* ps[2] = {pa, pb};
-    if ((st = enqueue_pyramids(g, xs, 2, ps, workspace, s)) != SPAMM_OK) return st;
-    return enqueue_plan(g, pa, pb, tau, false, offsets, klist, pairs, workspace, s);
+    return enqueue_prepare(g, a, b, tau, offsets, klist, pairs, workspace, static_cast<hipStream_t>(stream), false);
+}
+
+spamm_status spamm_prepare_schedule(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                    int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs,
+                                    void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    if (!a || !b || !offsets || !klist || !pairs) return fail(SPAMM_EINVAL, "null pointer");
+    if (!spamm_leaf_supported(leaf))
+        return fail(SPAMM_EUNSUPPORTED, "leaf %d has no multiply kernel (16, 32, 64, 128)", leaf);
+    spamm_status st = check_tau(tau);
+    if (st != SPAMM_OK) return st;
+    if ((st = check_grid(g)) != SPAMM_OK) return st;
+    if ((st = check_workspace(g, workspace, workspace_bytes)) != SPAMM_OK) return st;
+    if (klist_capacity < g.ntiles * g.bdim)
+        return fail(SPAMM_ENOSPACE, "klist capacity %lld < bdim^3 = %lld", (long long)klist_capacity,
+                    (long long)(g.ntiles * g.bdim));
+    return enqueue_prepare(g, a, b, tau, offsets, klist, pairs, workspace, static_cast<hipStream_t>(stream), true);
 }
 
 namespace {
@@ -459,10 +565,9 @@ spamm_status spamm_multiply(const float* a, const float* b, int64_t n, double ta
         return enqueue_small(g, a, b, tau, c, np, workspace, static_cast<hipStream_t>(stream));
     int32_t* offsets = at<int32_t>(workspace, L.offsets);
     int32_t* klist = at<int32_t>(workspace, L.klist);
-    st = spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
-                       stream);
-    if (st != SPAMM_OK) return st;
-    return spamm_execute(a, b, n, leaf, offsets, klist, c, workspace, workspace_bytes, stream);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = enqueue_prepare(g, a, b, tau, offsets, klist, np, workspace, s, true)) != SPAMM_OK) return st;
+    return enqueue_multiply(g, a, b, offsets, klist, c, workspace, s);
 }
 
 size_t spamm_split_bytes(int64_t n, int32_t precision) {
@@ -647,14 +752,25 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
             overlaps(split, sb, c, mbytes))
             return fail(SPAMM_EINVAL, "split buffer null or overlapping a, b or c");
     }
-    st = f16 ? spamm_prepare_scales(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, split, split_bytes,
-                                    workspace, workspace_bytes, stream)
-             : spamm_prepare(a, b, n, tau, leaf, offsets, klist, g.ntiles * g.bdim, np, workspace, workspace_bytes,
-                             stream);
-    if (st != SPAMM_OK) return st;
+    if (f16) {  // the scale exponents go to the split buffer's 256-byte header
+        const size_t mbytes = sizeof(float) * size_t(n) * size_t(n);
+        if (!split || (reinterpret_cast<uintptr_t>(split) & 255u) != 0)
+            return fail(SPAMM_EINVAL, "the split header must be non-null and 256-byte aligned");
+        if (split_bytes < kSplitHeaderBytes)
+            return fail(SPAMM_ENOSPACE, "header of %zu bytes, %zu needed", split_bytes, kSplitHeaderBytes);
+        if (overlaps(split, kSplitHeaderBytes, a, mbytes) || overlaps(split, kSplitHeaderBytes, b, mbytes) ||
+            overlaps(split, kSplitHeaderBytes, c, mbytes))
+            return fail(SPAMM_EINVAL, "header overlaps a, b or c");
+    }
+    // norms, pyramids, then the plan and the multiply schedule in one launch
+    if ((st = enqueue_prepare(g, a, b, tau, offsets, klist, np, workspace, s, true)) != SPAMM_OK) return st;
+    const spamm::SplitLayout SL = split_layout(split, n, precision);
+    if (f16 && (st = hip_check(spamm::launch_split_scales(g.bdim, g.lv, at<double>(workspace, L.pyr[0]),
+                                                          at<double>(workspace, L.pyr[1]), SL.exps, s),
+                               "scale kernels")) != SPAMM_OK)
+        return st;
     const int64_t per_tile = f16 ? kF16x3StagedPairsPerTile : kBf16StagedPairsPerTile;
     spamm::PairGate staged{np, per_tile * g.bdim * g.bdim, 1}, fused{};
-    const spamm::SplitLayout SL = split_layout(split, n, precision);
     if (planes) {
         fused = staged;
         fused.when_at_least = 0;
@@ -662,7 +778,6 @@ spamm_status spamm_multiply_precision(const float* a, const float* b, int64_t n,
             SPAMM_OK)
             return st;
     }
-    if ((st = enqueue_schedule(g, offsets, klist, workspace, s)) != SPAMM_OK) return st;
     if (planes &&
         (st = hip_check(spamm::launch_lowp_multiply(SL, c, n, g.bdim, precision, at<uint32_t>(workspace, L.mitems),
                                                     at<int32_t>(workspace, L.mprefix), device_cus(), staged, s),

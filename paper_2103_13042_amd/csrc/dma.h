@@ -59,8 +59,10 @@ __device__ __forceinline__ void wait_copies(int stores) {
 }
 
 // The copy-completion waits above count this kernel's own memory operations;
-// a register spill would add scratch accesses to that count.  Kernels that
-// rely on the count are checked once per process to use no scratch memory.
+// a register spill would add scratch accesses to that count, and in any
+// multiply kernel it would put slow scratch traffic in the inner loop.  Every
+// multiply kernel is checked once per process to use no scratch memory (a
+// kernel that does is not launched: hipErrorInvalidDeviceFunction).
 template <typename K>
 static hipError_t check_no_scratch(K kernel, int* state) {
     if (*state == 0) {

@@ -29,7 +29,7 @@ bool make_geom(int64_t n, int32_t leaf, Geom* g);
 // Workspace regions, in order.  Every entry point uses a subset.
 struct Layout {
     size_t spyr[2], pyr[2], counts, bsums, boffs, masks, offsets, klist, pair_scratch, mwords, mcount, mprefix,
-        mitems, items128, uprefix128, bounds, fix_slots, fix_slot_bytes, pairs, scalars, partials, total;
+        mitems, items128, uprefix128, bounds, fix_slots, fix_slot_bytes, pm_state, pairs, scalars, partials, total;
     bool leaf128_dma;  // leaf 128 runs on the LDS-DMA kernel (items128, uprefix128 in use)
 };
 
@@ -45,13 +45,21 @@ bool aligned16(const void* p);
 int device_cus();
 
 spamm_status check_grid(const Geom& g);
-spamm_status check_workspace(const Geom& g, void* ws, size_t bytes);
+// A null ws is replaced by the calling device's cached workspace (allocated
+// or grown here); otherwise bytes must cover the layout of g.
+spamm_status check_workspace(const Geom& g, void*& ws, size_t& bytes);
 spamm_status check_tau(double tau);
 spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const float* c);
 
-// Norm pass and pyramid for nmat matrices whose pyramids go to pyr_out[m].
+// Norm pass and pyramid for nmat matrices whose pyramids go to pyr_out[m];
+// the norm pass also zeroes clear_count int64 words at clear (if not null).
 spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
-                              hipStream_t s);
+                              hipStream_t s, int64_t* clear = nullptr, int64_t clear_count = 0);
+// Norms, pyramids and plan of A and B into the workspace pyramids and the
+// caller's offsets, klist, pairs; with `schedule` (leaf 32 or 64) also the
+// multiply schedule, the plan and schedule then coming from one launch.
+spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, double tau, int32_t* offsets,
+                             int32_t* klist, int64_t* pairs, void* ws, hipStream_t s, bool schedule);
 // Plan of the kept triples (norm product >= tau), or with `skipped` of the
 // triples SpAMM drops (norm product < tau).
 spamm_status enqueue_plan(const Geom& g, const double* pa, const double* pb, double tau, bool skipped,

@@ -15,10 +15,11 @@ __host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << 
 // kernels (A and B of one product).
 struct NormJob {
     const float* x[2];
-    double* sumsq[2];  // leaf sums of squares, row stride ld, or null
-    double* norms[2];  // leaf norms, row stride ld, or null
-    int64_t ld;        // row stride of the outputs (bdim, or the padded pyramid side)
-    int64_t* clear;    // one device int64 set to zero by the launch, or null
+    double* sumsq[2];     // leaf sums of squares, row stride ld, or null
+    double* norms[2];     // leaf norms, row stride ld, or null
+    int64_t ld;           // row stride of the outputs (bdim, or the padded pyramid side)
+    int64_t* clear;       // device int64 words set to zero by the launch, or null
+    int64_t clear_count;  // how many (1 when clear is set and this is 0)
 };
 
 // The leaf level of both pyramids is written by the norm pass (stride = side);
@@ -55,6 +56,26 @@ hipError_t launch_plan_scan(const int32_t* block_sums, int64_t nblocks, int32_t*
 hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* counts, const int32_t* block_offsets,
                             int64_t bdim, int32_t* offsets, int32_t* klist, hipStream_t s);
 
+// Plan and macro-tile schedule in one launch (plan_macro.hip; leaf 32 and 64,
+// bdim <= 1024): the outputs of launch_plan_mask + launch_plan_scan +
+// launch_plan_fill (offsets, klist, pairs) and of launch_macro_schedule
+// (uprefix, items); masks is scratch of bdim * bdim * nwords words; flags
+// (mb words, mb = ceil(bdim / 2)) and the ticket after them must be zero
+// before the launch (kPlanMacroClearWords words from flags).
+struct PlanMacroOut {
+    uint64_t* masks;
+    int32_t* offsets;
+    int32_t* klist;
+    int64_t* pairs;  // may be null
+    int32_t* uprefix;
+    uint32_t* items;
+    unsigned long long* flags;
+    unsigned int* ticket;
+};
+inline int64_t plan_macro_clear_words(int64_t bdim) { return (bdim + 1) / 2 + 1; }
+hipError_t launch_plan_macro(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+                             const PlanMacroOut& o, hipStream_t s);
+
 // Small products (leaf 32, bdim <= kSmallMaxBdim, n % 4 == 0, a and b 16-byte
 // aligned): the threshold test on the leaf norms na / nb (row stride ld) and
 // the multiply of the kept pairs in one launch; adds the number of kept pairs
@@ -64,11 +85,17 @@ hipError_t launch_small_multiply(const float* a, const float* b, float* c, int64
                                  const double* na, const double* nb, int64_t ld, double tau, int64_t* pairs,
                                  hipStream_t s);
 
-// Multiply: persistent, cost-balanced multiply of the kept pairs into C.
+// Multiply: persistent, cost-balanced multiply of the kept pairs into C
+// (leaf 32, 64, 128; leaf 16 goes to launch_multiply_leaf16).
 // pair_scratch holds bdim^3 int32 (each group's packed (tile, k) pairs).
 hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, int32_t leaf, int64_t bdim,
                            const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
                            int num_cus, hipStream_t s);
+
+// Leaf 16: one wave per output tile, operands straight from global memory
+// into MFMA registers (multiply_leaf16.hip); every tile of c is written.
+hipError_t launch_multiply_leaf16(const float* a, const float* b, float* c, int64_t n, int64_t bdim,
+                                  const int32_t* offsets, const int32_t* klist, bool vec, hipStream_t s);
 
 // Multiply on 2x2 macro tiles (leaf 32 and 64), in two steps.  Schedule:
 // per-macro-tile k bitmaps into words [mb*mb*4*nwords], union sizes into

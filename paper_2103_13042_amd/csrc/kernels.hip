@@ -179,11 +179,68 @@ __device__ __forceinline__ void leaf_sumsq_strip(const float* __restrict__ x, in
     __syncthreads();  // prev is reused by the block's next strip
 }
 
+// words the first block of a norm pass sets to zero (a pair counter, the
+// look-back state of the plan that follows)
+__device__ __forceinline__ void clear_words(const NormJob& job) {
+    if (job.clear && (blockIdx.x | blockIdx.y | blockIdx.z) == 0) {
+        const int64_t cnt = job.clear_count > 0 ? job.clear_count : 1;
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) job.clear[e] = 0;
+    }
+}
+
 template <int LEAF, bool VEC, bool NT>
 __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_kernel(NormJob job, int64_t n, int64_t bdim) {
     const int m = blockIdx.z;
-    if (job.clear && (blockIdx.x | blockIdx.y | blockIdx.z | threadIdx.x) == 0) *job.clear = 0;
+    clear_words(job);
     leaf_sumsq_strip<LEAF, VEC, NT>(job.x[m], n, bdim, blockIdx.y, blockIdx.x, job.sumsq[m], job.norms[m], job.ld);
+}
+
+// Small matrices (too few strips to fill the GPU with the kernel above): 1024
+// threads per strip x 1024-column chunk, four row groups of LEAF/4 rows whose
+// loads are all in flight at once; the four partial sums of a column group
+// are added in row-group order through LDS, then across the tile's threads.
+// Rows 16-byte aligned (n % 4 == 0, x 16-byte aligned).
+constexpr int kNormSmallThreads = 1024;
+
+template <int LEAF>
+__global__ __launch_bounds__(kNormSmallThreads) void leaf_sumsq_small_kernel(NormJob job, int64_t n, int64_t bdim) {
+    constexpr int G = LEAF / 4;           // threads per tile (4 columns each)
+    constexpr int RPG = LEAF / 4;         // rows per row group
+    __shared__ double part[3][kNormCols / 4];
+    const int m = blockIdx.z;
+    clear_words(job);
+    const float* __restrict__ x = job.x[m];
+    const int t = threadIdx.x, cg = t & 255, rg = t >> 8;
+    const int64_t strip = blockIdx.y, col = int64_t(blockIdx.x) * kNormCols + 4 * cg;
+    const int64_t r0 = strip * LEAF + rg * RPG;
+    double acc = 0.0;
+    if (col < n) {
+        f4 v[RPG];
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+            const int64_t row = r0 + r;
+            v[r] = row < n ? *reinterpret_cast<const f4*>(x + row * n + col) : f4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+            a0 += double(v[r].x) * double(v[r].x) + double(v[r].y) * double(v[r].y);
+            a1 += double(v[r].z) * double(v[r].z) + double(v[r].w) * double(v[r].w);
+        }
+        acc = a0 + a1;
+    }
+    if (rg > 0) part[rg - 1][cg] = acc;
+    __syncthreads();
+    if (rg != 0) return;
+    double s = ((acc + part[0][cg]) + part[1][cg]) + part[2][cg];
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) s += __shfl_xor(s, off);
+    const int64_t tj = col / LEAF;
+    if ((cg % G) == 0 && col < n && tj < bdim) {
+        const int64_t i = strip * job.ld + tj;
+        if (job.sumsq[m]) job.sumsq[m][i] = s;
+        if (job.norms[m]) job.norms[m][i] = sqrt(s);
+    }
 }
 
 // Any other leaf size: one block per tile, strided over its elements.
@@ -191,7 +248,7 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_generic_kernel(NormJo
                                                                           int32_t leaf) {
     __shared__ double partial[kNormThreads / 64];
     const int m = blockIdx.z;
-    if (job.clear && (blockIdx.x | blockIdx.y | blockIdx.z | threadIdx.x) == 0) *job.clear = 0;
+    clear_words(job);
     const float* __restrict__ x = job.x[m];
     const int64_t ti = blockIdx.y, tj = blockIdx.x;
     const int64_t rows = (ti * leaf + leaf < n ? leaf : n - ti * leaf);
@@ -215,12 +272,20 @@ __global__ __launch_bounds__(kNormThreads) void leaf_sumsq_generic_kernel(NormJo
 }
 
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;  // MI355X's last-level cache
+constexpr int64_t kSmallNormBlocks = 256;                      // one block per CU
 
 template <int LEAF>
 static hipError_t launch_leaf_fixed(const NormJob& job, int nmat, int64_t n, int64_t bdim, bool vec,
                                     hipStream_t s) {
     dim3 grid(unsigned((n + kNormCols - 1) / kNormCols), unsigned(bdim), unsigned(nmat));
     const bool nt = 4.0 * double(n) * double(n) * nmat > kInfinityCacheBytes;
+    if constexpr (LEAF == 16 || LEAF == 32 || LEAF == 64) {
+        // fewer blocks than CUs: the four-row-group form keeps more loads in flight
+        if (vec && int64_t(grid.x) * grid.y * grid.z < kSmallNormBlocks) {
+            leaf_sumsq_small_kernel<LEAF><<<grid, kNormSmallThreads, 0, s>>>(job, n, bdim);
+            return hipGetLastError();
+        }
+    }
     if (vec && nt)
         leaf_sumsq_kernel<LEAF, true, true><<<grid, kNormThreads, 0, s>>>(job, n, bdim);
     else if (vec)
@@ -601,7 +666,7 @@ constexpr int kRing = 512;  // packed pairs held in LDS (a power of two)
 #define SPAMM_OCC32 2
 #endif
 #ifndef SPAMM_OCC128
-#define SPAMM_OCC128 2
+#define SPAMM_OCC128 1
 #endif
 template <int LEAF>
 struct MulCfg;
@@ -615,6 +680,8 @@ struct MulCfg<64> {
 };
 template <>
 struct MulCfg<128> {
+    // one workgroup per CU: at two (256 registers per lane) the kernel spilled
+    // to scratch, also with 16 k per stage
     static constexpr int MF = 32, KC = 32, OCC = SPAMM_OCC128;
 };
 
@@ -904,6 +971,10 @@ static hipError_t launch_mul(const float* a, const float* b, float* c, int64_t n
     const int64_t cap = ((nt + 7) / 8) * 8;
     if (groups > cap) groups = cap;
     groups = ((groups + 7) / 8) * 8;
+    static int scratch_state[2] = {0, 0};
+    const hipError_t ce = vec ? check_no_scratch(multiply_kernel<LEAF, true>, &scratch_state[1])
+                              : check_no_scratch(multiply_kernel<LEAF, false>, &scratch_state[0]);
+    if (ce != hipSuccess) return ce;
     if (vec)
         multiply_kernel<LEAF, true>
             <<<unsigned(groups), kMulThreads, 0, s>>>(a, b, c, n, bdim, offsets, klist, pair_scratch);
@@ -917,6 +988,7 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
                            const int32_t* offsets, const int32_t* klist, int32_t* pair_scratch, bool vec,
                            int num_cus, hipStream_t s) {
     switch (leaf) {
+        case 16: return launch_multiply_leaf16(a, b, c, n, bdim, offsets, klist, vec, s);
         case 32: return launch_mul<32>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
         case 64: return launch_mul<64>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
         case 128: return launch_mul<128>(a, b, c, n, bdim, offsets, klist, pair_scratch, vec, num_cus, s);
@@ -1137,9 +1209,14 @@ __device__ __forceinline__ int64_t batch_macro_partition(const BatchProduct& q, 
 }
 
 // Leaf 32 and 64: a persistent grid over the class's macro tiles (all its
-// products in turn), each workgroup a contiguous range of equal cost.
+// products in turn), each workgroup a contiguous range of equal cost.  Three
+// workgroups per CU: the kernel holds both the aligned and the unaligned form
+// of the macro-tile multiply, and at four per CU (128 registers per lane) it
+// spilled to scratch.
+constexpr int kBatchMacOcc = 3;
+
 template <int LEAF>
-__global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_batch_macro_kernel(
+__global__ __launch_bounds__(kMacThreads, kBatchMacOcc) void multiply_batch_macro_kernel(
     const BatchProduct* __restrict__ P, const int32_t* __restrict__ members, int32_t nmem,
     const int64_t* __restrict__ class_total, int cls) {
     __shared__ __attribute__((aligned(16))) float lds[2 * MacGeom<LEAF>::STAGE];
@@ -1239,14 +1316,19 @@ hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t*
                                        class_count_host[1], class_count_host[2], class_total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    static int scratch_state[3] = {0, 0, 0};
+    if ((e = check_no_scratch(multiply_batch_macro_kernel<32>, &scratch_state[0])) != hipSuccess ||
+        (e = check_no_scratch(multiply_batch_kernel<64>, &scratch_state[1])) != hipSuccess ||
+        (e = check_no_scratch(multiply_batch_kernel<128>, &scratch_state[2])) != hipSuccess)
+        return e;
     int32_t first = 0;
     for (int c = 0; c < kBatchClasses; ++c) {
         const int32_t nmem = class_count_host[c];
         if (nmem > 0) {
-            const unsigned groups = unsigned(num_cus * 2);
+            const unsigned groups = unsigned(num_cus * (c == 1 ? MulCfg<64>::OCC : MulCfg<128>::OCC));
             switch (c) {
                 case 0:
-                    multiply_batch_macro_kernel<32><<<unsigned(num_cus * MacGeom<32>::OCC), kMacThreads, 0, s>>>(
+                    multiply_batch_macro_kernel<32><<<unsigned(num_cus * kBatchMacOcc), kMacThreads, 0, s>>>(
                         prods, members + first, nmem, class_total, c);
                     break;
                 case 1:

@@ -456,6 +456,10 @@ static hipError_t launch_macro_run(const float* a, const float* b, float* c, int
     int64_t groups = int64_t(num_cus) * MacGeom<LEAF>::OCC;
     if (groups > cap) groups = cap;
     groups = ((groups + 7) / 8) * 8;
+    static int scratch_state[2] = {0, 0};
+    const hipError_t ce = vec ? check_no_scratch(multiply_macro_kernel<LEAF, true>, &scratch_state[1])
+                              : check_no_scratch(multiply_macro_kernel<LEAF, false>, &scratch_state[0]);
+    if (ce != hipSuccess) return ce;
     if (vec)
         multiply_macro_kernel<LEAF, true>
             <<<unsigned(groups), kMacThreads, 0, s>>>(a, b, c, n, bdim, mb, ms.items, ms.uprefix);

@@ -6,7 +6,10 @@
 // the multiply has too few macro tiles to give every SIMD more than one wave.
 //
 // One workgroup per 2x2 block of output tiles (macro tile (I, J)), sixteen
-// waves in four k-groups of four (wave 4g+q: k-group g, output tile q = 2a+b):
+// waves in four k-groups of four (wave w: k-group g = w >> 2, output tile
+// q = 2a+b = (w + g) & 3, so the four waves w, w+4, w+8, w+12 that share a
+// SIMD hold the four different tiles and every SIMD gets a quarter of each
+// tile's entries, whichever tiles keep more k):
 //  * every wave tests, lane k for every k < bdim, the four products
 //    nA[2I+a][k] * nB[k][2J+b] >= tau (the comparison of the plan kernel, on the
 //    same leaf norms, so the kept pairs are the same; the pyramid only skips
@@ -23,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "dma.h"
 #include "internal.h"
 
 namespace spamm {
@@ -41,7 +45,7 @@ __global__ __launch_bounds__(kSmallWaves * 64, 1) void multiply_small_kernel(
     __shared__ float red[kSmallGroups - 1][4][16][64];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int grp = wave >> 2, q = wave & 3, wa = q >> 1, wb = q & 1;
+    const int grp = wave >> 2, q = (wave + grp) & 3, wa = q >> 1, wb = q & 1;
     const int ir = lane & 31, g = lane >> 5;
     const int64_t m = blockIdx.x;
     const int64_t I = m / mb, J = m - (m / mb) * mb;
@@ -157,6 +161,9 @@ hipError_t launch_small_multiply(const float* a, const float* b, float* c, int64
                                  hipStream_t s) {
     if (bdim < 1 || bdim > kSmallMaxBdim || n > bdim * kSmallLeaf || n % 4 != 0) return hipErrorInvalidValue;
     const int64_t mb = (bdim + 1) / 2;
+    static int scratch_state = 0;
+    const hipError_t ce = check_no_scratch(multiply_small_kernel, &scratch_state);
+    if (ce != hipSuccess) return ce;
     multiply_small_kernel<<<unsigned(mb * mb), kSmallWaves * 64, 0, s>>>(
         a, b, c, n, bdim, mb, na, nb, ld, tau, reinterpret_cast<unsigned long long*>(pairs));
     return hipGetLastError();

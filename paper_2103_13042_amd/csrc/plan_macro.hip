@@ -1,0 +1,313 @@
+// The pruning plan and the macro-tile schedule of the multiply in one launch
+// (leaf 32 and 64): the work of plan_mask, plan_scan, plan_fill (the bitmap,
+// map_offset and validNum of Algorithm 2, and Algorithm 1's norm tests with
+// whole k-ranges settled on a pyramid node as in the plan kernel) and of
+// macro_words, its scan and macro_items (the union k-lists of 2x2 blocks of
+// output tiles that the multiply streams, section 3.5.1's balanced work
+// split reads their prefix), with identical outputs.
+//
+// One workgroup per macro-tile row I (output tile rows 2I and 2I+1), taken in
+// order of a ticket so that every lower row's workgroup has started:
+//  1. the tests: per k-chunk of 64 (one pyramid node of 64 x 64 leaf tiles on
+//     each side settles the chunk for 64 tile columns when its product is
+//     below tau), B's leaf norms staged in LDS, one ballot per (tile, chunk)
+//     gives the bitmap of kept k; per tile the count V, per macro tile the
+//     size of the union of its four bitmaps;
+//  2. the row's two sums (kept pairs, union entries) are combined with those
+//     of the rows before it by a decoupled look-back: each row publishes its
+//     sums, then its inclusive prefix, in one 64-bit word per row written and
+//     read with device-scope atomics (the payload is the word itself, so no
+//     other memory needs to be made visible across XCDs); one wave reads 64
+//     predecessors' words at a time;
+//  3. offsets and the ascending k-lists of the row's tiles, the union prefix
+//     and packed items of its macro tiles.
+// The look-back words and the ticket must be zero before the launch (the
+// leaf norm pass clears them).
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+#include "macro.h"
+
+namespace spamm {
+
+namespace {
+constexpr int kPmThreads = 256;
+constexpr int kPmWaves = kPmThreads / 64;
+constexpr int64_t kPmMaxBdim = 1024;
+constexpr int kPmMaxNw = int(kPmMaxBdim / 64);
+constexpr uint32_t kPmMaxSpins = 1u << 22;
+
+// look-back word: state in bits 62-63 (1: the row's own sums, 2: inclusive
+// prefix), kept pairs in bits 31-61, union entries in bits 0-30
+constexpr unsigned long long kStAgg = 1ull << 62, kStIncl = 2ull << 62;
+constexpr unsigned long long kField = (1ull << 31) - 1;
+
+__device__ __forceinline__ unsigned long long pack_sums(unsigned long long pairs, unsigned long long uni) {
+    return (pairs << 31) | uni;
+}
+
+__device__ __forceinline__ unsigned long long atomic_load_agent(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_store_agent(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+}  // namespace
+
+__global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __restrict__ pyr_a,
+                                                                const double* __restrict__ pyr_b, int64_t bdim,
+                                                                int lv, double tau, PlanMacroOut o) {
+    __shared__ double sb[64][65];                    // B leaf norms of a chunk: [k][j]
+    __shared__ int32_t tcount[2][kPmMaxBdim];        // V of the row pair's tiles
+    __shared__ int32_t ucnt[kPmMaxBdim / 2];         // union sizes of the row's macro tiles
+    __shared__ uint32_t skip[kPmMaxNw];              // bit c of word jb: chunk c settled as empty
+    __shared__ int64_t wsum[2][kPmWaves];
+    __shared__ unsigned long long s_excl;
+    __shared__ int64_t s_row;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_row = atomicAdd(o.ticket, 1u);
+    const int64_t side = int64_t(1) << lv;
+    const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
+    const int nw = int((bdim + 63) / 64);
+    const double* la = pyr_a + level_offset(lv);
+    const double* lb = pyr_b + level_offset(lv);
+    __syncthreads();
+    const int64_t I = s_row;
+    if (I >= mb) return;       // only if the ticket was not cleared before the launch
+    const int64_t r0 = 2 * I;  // tile rows r0 and r0 + 1 (the latter may lie outside the grid)
+
+    // ---- 1. tests, bitmaps, counts
+    for (int64_t jb = 0; jb < nw; ++jb) {
+        // wave w: macro columns J = 32 jb + w + 4 u (u = 0..7) of this column block
+        int cnt[8][4];
+        int uc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            uc[u] = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cnt[u][q] = 0;
+        }
+        uint32_t skipbits = 0;
+        for (int c = 0; c < nw; ++c) {
+            bool below;
+            if (lv >= 6) {
+                const int lc = lv - 6;
+                const int64_t w = int64_t(1) << lc;
+                below = !(pyr_a[level_offset(lc) + (r0 >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + jb] >=
+                          tau);
+            } else {
+                below = !(pyr_a[0] * pyr_b[0] >= tau);
+            }
+            if (below) {  // no triple of the chunk is kept, for any tile of the block
+                skipbits |= 1u << c;
+                continue;
+            }
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + u * kPmThreads;
+                const int64_t k = int64_t(c) * 64 + (e >> 6), j = jb * 64 + (e & 63);
+                v[u] = (k < side && j < side) ? lb[k * side + j] : 0.0;
+            }
+            const int64_t k = int64_t(c) * 64 + lane;
+            const double a0 = k < side ? la[r0 * side + k] : 0.0;
+            const double a1 = (k < side && r0 + 1 < side) ? la[(r0 + 1) * side + k] : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + u * kPmThreads;
+                sb[e >> 6][e & 63] = v[u];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int jj = 2 * (wave + 4 * u);  // first tile column of macro column J, in the block
+                uint64_t uni = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int h = q >> 1, bcol = q & 1;
+                    const int64_t r = r0 + h, j = jb * 64 + jj + bcol;
+                    const double p = (h ? a1 : a0) * sb[lane][jj + bcol];
+                    const uint64_t mk = __ballot(p >= tau && k < bdim && r < bdim && j < bdim);
+                    if (lane == 0 && r < bdim && j < bdim) o.masks[(r * bdim + j) * nw + c] = mk;
+                    cnt[u][q] += __popcll(mk);
+                    uni |= mk;
+                }
+                uc[u] += __popcll(uni);
+            }
+        }
+        if (tid == 0) skip[jb] = skipbits;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t J = jb * 32 + wave + 4 * u;
+            if (lane == 0) {
+                if (J < mb) ucnt[J] = uc[u];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t j = 2 * J + (q & 1);
+                    if (j < bdim) tcount[q >> 1][j] = cnt[u][q];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. the row's sums, then the look-back over the rows before it
+    {
+        int64_t sp = 0, su = 0;
+        for (int64_t e = tid; e < 2 * bdim; e += kPmThreads) {
+            const int h = int(e / bdim);
+            if (r0 + h < bdim) sp += tcount[h][e - h * bdim];
+        }
+        for (int64_t e = tid; e < mb; e += kPmThreads) su += ucnt[e];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            sp += __shfl_xor(sp, off);
+            su += __shfl_xor(su, off);
+        }
+        if (lane == 0) {
+            wsum[0][wave] = sp;
+            wsum[1][wave] = su;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        unsigned long long own_p = 0, own_u = 0;
+#pragma unroll
+        for (int w = 0; w < kPmWaves; ++w) {
+            own_p += (unsigned long long)wsum[0][w];
+            own_u += (unsigned long long)wsum[1][w];
+        }
+        const unsigned long long own = pack_sums(own_p, own_u);
+        if (lane == 0) atomic_store_agent(o.flags + I, (I == 0 ? kStIncl : kStAgg) | own);
+        // exclusive prefix: walk back in windows of 64 rows; lane l reads row
+        // top - l; the window ends at the nearest inclusive prefix, and every
+        // row after it must have published its sums
+        unsigned long long ex_p = 0, ex_u = 0;
+        int64_t top = I - 1;
+        // every wait ends: rows below I have all started (ticket order) and
+        // publish without waiting on later rows; the spin is still bounded
+        // (seconds), after which the plan is marked invalid (pairs = -1)
+        uint32_t spins = 0;
+        bool timed_out = false;
+        while (top >= 0) {
+            const int64_t p = top - lane;
+            unsigned long long wv = p >= 0 ? atomic_load_agent(o.flags + p) : kStIncl;
+            uint64_t incl = __ballot((wv >> 62) == 2);
+            uint64_t ready = __ballot((wv >> 62) != 0);
+            // lanes up to and including the first inclusive one must all be ready
+            const int first = incl ? __ffsll((unsigned long long)incl) - 1 : 63;
+            const uint64_t need = first == 63 ? ~0ull : ((2ull << first) - 1);
+            if ((ready & need) != need) {
+                if (++spins > kPmMaxSpins) {
+                    timed_out = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                continue;  // re-read the same window
+            }
+            unsigned long long cp = 0, cu = 0;
+            if (lane <= first && p >= 0) {
+                cp = (wv >> 31) & kField;
+                cu = wv & kField;
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                cp += __shfl_xor(cp, off);
+                cu += __shfl_xor(cu, off);
+            }
+            ex_p += cp;
+            ex_u += cu;
+            if (incl) break;
+            top -= 64;
+        }
+        if (lane == 0) {
+            if (I > 0) atomic_store_agent(o.flags + I, kStIncl | pack_sums(ex_p + own_p, ex_u + own_u));
+            s_excl = pack_sums(ex_p, ex_u);
+            if (I == mb - 1) {  // the last row: totals
+                o.offsets[bdim * bdim] = int32_t(ex_p + own_p);
+                o.uprefix[nm] = int32_t(ex_u + own_u);
+                if (o.pairs) *o.pairs = int64_t(ex_p + own_p);
+            }
+            if (timed_out && o.pairs) *o.pairs = -1;
+        }
+    }
+    __syncthreads();
+
+    // ---- 3. offsets, k-lists, union prefix, items
+    const int64_t base_p = int64_t((s_excl >> 31) & kField), base_u = int64_t(s_excl & kField);
+    // in-row exclusive prefixes of the counts, in place (one wave per array)
+    if (wave < 3) {
+        int32_t* arr = wave < 2 ? tcount[wave] : ucnt;
+        const int64_t len = wave < 2 ? (r0 + wave < bdim ? bdim : 0) : mb;
+        int32_t run = 0;
+        for (int64_t b0 = 0; b0 < len; b0 += 64) {
+            const int64_t e = b0 + lane;
+            const int32_t v = e < len ? arr[e] : 0;
+            int32_t incl = v;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int32_t up = __shfl_up(incl, off);
+                if (lane >= off) incl += up;
+            }
+            if (e < len) arr[e] = run + incl - v;
+            run += __shfl(incl, 63);
+        }
+        if (wave < 2 && lane == 0) wsum[0][wave] = run;  // the tile row's total
+    }
+    __syncthreads();
+    const uint64_t below_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // tiles: one wave per tile of rows r0, r0 + 1
+    for (int64_t e = wave; e < 2 * bdim; e += kPmWaves) {
+        const int h = int(e / bdim);
+        const int64_t j = e - h * bdim, r = r0 + h;
+        if (r >= bdim) break;
+        const int64_t t = r * bdim + j;
+        int64_t base = base_p + (h ? wsum[0][0] : 0) + tcount[h][j];
+        if (lane == 0) o.offsets[t] = int32_t(base);
+        const uint32_t sk = skip[j >> 6];
+        for (int c = 0; c < nw; ++c) {
+            if ((sk >> c) & 1u) continue;
+            const uint64_t m = o.masks[t * nw + c];
+            if ((m >> lane) & 1ull) o.klist[base + __popcll(m & below_mask)] = c * 64 + lane;
+            base += __popcll(m);
+        }
+    }
+    // macro tiles: one wave per macro tile of row I; the union of the four
+    // bitmaps, items in ascending k (macro_items_wave's packing)
+    for (int64_t J = wave; J < mb; J += kPmWaves) {
+        const int64_t m = I * mb + J;
+        int64_t base = base_u + ucnt[J];
+        if (lane == 0) o.uprefix[m] = int32_t(base);
+        const uint32_t sk = skip[(2 * J) >> 6];
+        for (int c = 0; c < nw; ++c) {
+            if ((sk >> c) & 1u) continue;
+            uint64_t w4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + (q >> 1), j = 2 * J + (q & 1);
+                w4[q] = (r < bdim && j < bdim) ? o.masks[(r * bdim + j) * nw + c] : 0ull;
+            }
+            const uint64_t u = w4[0] | w4[1] | w4[2] | w4[3];
+            if ((u >> lane) & 1ull) {
+                const uint32_t mem = uint32_t((w4[0] >> lane) & 1) | uint32_t(((w4[1] >> lane) & 1) << 1) |
+                                     uint32_t(((w4[2] >> lane) & 1) << 2) | uint32_t(((w4[3] >> lane) & 1) << 3);
+                o.items[base + __popcll(u & below_mask)] = mi_pack(uint32_t(I), uint32_t(J), uint32_t(c * 64 + lane), mem);
+            }
+            base += __popcll(u);
+        }
+    }
+}
+
+hipError_t launch_plan_macro(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
+                             const PlanMacroOut& o, hipStream_t s) {
+    if (bdim < 1 || bdim > kPmMaxBdim) return hipErrorInvalidValue;
+    const int64_t mb = (bdim + 1) / 2;
+    plan_macro_kernel<<<unsigned(mb), kPmThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, o);
+    return hipGetLastError();
+}
+
+}  // namespace spamm

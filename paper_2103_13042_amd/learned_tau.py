@@ -172,7 +172,8 @@ def compare(params: torch.Tensor, problems, targets, *, max_evals: int = 64):
         err_g, dropped_g = pr.error(guess)
         total = sp.bdim(pr.n, pr.leaf) ** 3
         rows.append({
-            "n": pr.n, "target": target, "tau": tau0, "tau_seeded": tau1, "evals_scratch": ev0,
+            "n": pr.n, "target": target, "tau": tau0, "tau_seeded": tau1, "err": err0, "err_seeded": err1,
+            "evals_scratch": ev0,
             "evals_seeded": ev1, "ms_scratch": 1e3 * (t1 - t0), "ms_seeded": 1e3 * (t2 - t1),
             "tau_pred": guess, "log10_ratio_pred": math.log10(guess / tau0) if tau0 > 0 else None,
             "err_pred": err_g, "pred_meets_target": err_g <= target,

@@ -51,7 +51,7 @@ def test_geometry_queries(lib):
     assert b.levels(1024, 32) == 5 and b.levels(1000, 64) == 4 and b.levels(5, 8) == 0 and b.levels(8192, 64) == 7
     assert b.pyramid_size(8192, 64) == sum(4**l for l in range(8)) == 21845
     assert b.pyramid_size(1100, 32) == sum(4**l for l in range(7))  # bdim 35 -> padded to 64
-    assert [b.leaf_supported(x) for x in (16, 32, 64, 128, 48)] == [False, True, True, True, False]
+    assert [b.leaf_supported(x) for x in (16, 32, 64, 128, 48, 8)] == [True, True, True, True, False, False]
     ws = b.workspace_bytes(8192, 64)
     assert ws >= 4 * 128**3  # the worst-case k-list alone
     assert b.workspace_bytes(8192, 4) == 0  # 2048 tiles per side is over the limit
@@ -86,7 +86,7 @@ def test_multiply_argument_checks(lib):
     assert _mul(lib, c=_FAKE_B + 4) == 1  # C overlaps B
     assert b"overlaps" in lib.spamm_last_error()
     assert _mul(lib, leaf=48, wsb=1 << 30) == 4  # no multiply kernel for this leaf
-    assert _mul(lib, ws=0) == 1
+    assert _mul(lib, leaf=48, ws=0) == 4  # checked before a NULL workspace is resolved
     assert _mul(lib, wsb=16) == 2  # workspace too small
     assert b"needed" in lib.spamm_last_error()
 
@@ -114,3 +114,13 @@ def test_binding_rejects_cpu_tensors():
     x = torch.zeros(8, 8)
     with pytest.raises(TypeError):
         bd.norms(x, 4)
+
+
+def test_gfx950_code_has_no_packed_fp32_instructions():
+    # v_pk_{fma,mul,add}_f32 are kept out of the library (the device pass gets
+    # -packed-fp32-ops); checked on the gfx950 code objects of the last build
+    from paper_2103_13042_amd import build as b
+
+    if not list(b.BUILD.glob("*.hipfb")):
+        pytest.skip("no device bundles in the build folder (library not built here)")
+    assert b.packed_fp32_instructions() == []

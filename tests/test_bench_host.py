@@ -6,6 +6,7 @@ from __future__ import annotations
 import json
 import subprocess
 import sys
+import types
 from pathlib import Path
 
 import bench
@@ -36,8 +37,11 @@ def test_traffic_record_scales_each_counter_by_the_calibration_copy(tmp_path, mo
                                                     (fix, 50.0), (fix, 50.0)])
     _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", calib_kib), (mul, 300.0),
                                                     (mul, 300.0), (fix, 20.0), (fix, 20.0)])
-    assert bench.write_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 8192, 64, 1e-6, ["cmd"]) == 0
-    rec = json.loads((tmp_path / "traffic.json").read_text())
+    args = types.SimpleNamespace(n=8192, leaf=64, tau=1e-6, workload="alg", alpha=0.05, precision="fp32")
+    assert bench.write_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), args, ["cmd"]) == 0
+    recs = json.loads((tmp_path / "traffic.json").read_text())["records"]
+    assert len(recs) == 1
+    rec = recs[0]
     assert rec["kernel"] == "multiply_macro_dma_kernel + macro_fixup_kernel"
     assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
     # per launch: (mean 1100 + 50) KiB read x 2, (300 + 20) KiB written x 1
@@ -45,6 +49,12 @@ def test_traffic_record_scales_each_counter_by_the_calibration_copy(tmp_path, mo
     k, src = bench.multiply_kernel(8192, 64)
     assert bench.traffic_entry(k, src, bench.workload_name(8192, 64, 1e-6)) == rec
     assert bench.traffic_entry(k, src, bench.workload_name(8192, 64, 1e-8)) is None  # another workload
+    # a second workload adds a record; the same workload again replaces its own
+    args.tau = 1e-8
+    assert bench.write_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), args, ["cmd"]) == 0
+    assert bench.write_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), args, ["cmd"]) == 0
+    assert len(json.loads((tmp_path / "traffic.json").read_text())["records"]) == 2
+    assert bench.traffic_entry(k, src, bench.workload_name(8192, 64, 1e-6)) == rec
 
 
 def test_traffic_record_key_ignores_comments_but_not_code():

@@ -100,7 +100,7 @@ def test_graph_replays_equal_eager_run(batch):
 def test_batch_argument_errors():
     a = torch.ones(64, 64, device=DEV)
     with pytest.raises(sp.SpammError):
-        sp.Batch([a], [a], [16], [1e-6])  # leaf 16 has no multiply kernel
+        sp.Batch([a], [a], [16], [1e-6])  # leaf 16 is not a batched leaf class
     with pytest.raises(sp.SpammError):
         sp.Batch([a], [a], [32], [-1.0])
     with pytest.raises(ValueError):
@@ -137,3 +137,62 @@ def test_batch_with_members_that_are_only_4_byte_aligned():
         bound = n * U32 / (1 - n * U32) * abs_ref + 1e-38
         c = bt.c[q].cpu().numpy().astype(np.float64)
         assert np.all(np.abs(c - c_ref) <= bound), q
+
+
+# --------------------------------------------------------------------------
+# The benchmark batch at its real shape: 256 products, n log-uniform in
+# [256, 4096], exponential decay with rates uniform in [0.01, 0.5), tau = 1e-6,
+# leaves from the committed tuner table (as the benchmark picks them).  Every
+# product's pair count equals the oracle's (the count-only recursion over all
+# its output tiles); sampled output tiles of every product equal the oracle's
+# within the FP32 accumulation bound.
+
+BATCH_COUNT, BATCH_TAU, CHUNKS = 256, 1e-6, 4
+
+
+@pytest.fixture(scope="module")
+def bench_batch():
+    from paper_2103_13042_amd import autotune
+
+    specs = inputs.batch_specs(BATCH_COUNT)
+    table = autotune.load(autotune.TABLE_FILE)
+    a_l = [inputs.exp_decay_torch(n, aa, sa, DEV) for n, aa, _, sa, _ in specs]
+    b_l = [inputs.exp_decay_torch(n, ab, sb, DEV) for n, _, ab, _, sb in specs]
+    leaves = [autotune.choose(table, n, autotune.density(a, b, BATCH_TAU)) for (n, *_), a, b in zip(specs, a_l, b_l)]
+    bt = sp.Batch(a_l, b_l, leaves, [BATCH_TAU] * len(specs))
+    bt.run()
+    torch.cuda.synchronize()
+    print(f"batch of {len(specs)}: leaves {sorted(set(leaves))}, pairs {int(bt.pairs.sum())}", flush=True)
+    return specs, leaves, a_l, b_l, bt
+
+
+def _batch_tiles(bd: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    pick = {(0, 0), (bd - 1, bd - 1), (0, bd - 1)}
+    pick |= {(i, min(bd - 1, i + d)) for i in range(0, bd, max(1, bd // 3)) for d in (0, 1)}
+    pick |= {tuple(int(v) for v in rng.integers(0, bd, 2)) for _ in range(3)}
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+@pytest.mark.parametrize("chunk", range(CHUNKS))
+def test_benchmark_batch_matches_oracle(bench_batch, chunk):
+    specs, leaves, a_l, b_l, bt = bench_batch
+    per = len(specs) // CHUNKS
+    pairs = bt.pairs.cpu().tolist()
+    for q in range(chunk * per, (chunk + 1) * per):
+        n, leaf = specs[q][0], leaves[q]
+        a, b = a_l[q].cpu().numpy(), b_l[q].cpu().numpy()
+        pa, pb = oracle.pyramid(a, leaf), oracle.pyramid(b, leaf)
+        _, counts, _ = oracle.spamm_tiles(a, b, BATCH_TAU, leaf, oracle.all_tiles(n, leaf), products=False,
+                                          pyr_a=pa, pyr_b=pb)
+        assert pairs[q] == int(counts.sum()), (q, n, leaf)
+        tiles = _batch_tiles(oracle.bdim(n, leaf), q)
+        ct, _, _ = oracle.spamm_tiles(a, b, BATCH_TAU, leaf, tiles, pyr_a=pa, pyr_b=pb)
+        abs_t, _, _ = oracle.spamm_tiles(np.abs(a), np.abs(b), BATCH_TAU, leaf, tiles)
+        c = bt.c[q]
+        for (r0, c0, blk), (_, _, ab) in zip(oracle.tiles_to_matrix_view(ct, tiles, n, leaf),
+                                             oracle.tiles_to_matrix_view(abs_t, tiles, n, leaf)):
+            got = c[r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]].cpu().numpy().astype(np.float64)
+            bound = n * U32 / (1 - n * U32) * ab + 1e-38
+            assert np.all(np.abs(got - blk) <= bound), (q, n, leaf, r0, c0)
+    print(f"products {chunk * per}..{(chunk + 1) * per - 1}: pairs and sampled tiles equal the oracle", flush=True)

@@ -76,3 +76,33 @@ def test_committed_network_cuts_search_evaluations():
     seeded = np.mean([r["evals_seeded"] for r in rows])
     assert seeded < 0.8 * scratch, (seeded, scratch)
     assert np.median([abs(r["log10_ratio_pred"]) for r in rows]) < np.log10(2.0)
+
+
+EVAL_N, EVAL_TARGET, EVAL_PROBLEMS = 8192, 1e-4, 32
+
+
+def test_committed_network_at_the_evaluation_size():
+    """The committed network (trained at N = 2048) on unseen N = 8192 pairs at
+    relative-error target 1e-4: the seeded search returns the search's own
+    threshold and its certified error (the exact ||AB - SpAMM||_F / ||AB||_F,
+    the dropped pairs multiplied on the GPU) meets the target, for every
+    problem; evaluation counts and prediction errors are reported."""
+    p = lt.load_params(DEV)
+    leaf = 64
+    ws = sp.workspace(EVAL_N, leaf, DEV)
+    e = torch.empty((EVAL_N, EVAL_N), dtype=torch.float32, device=DEV)
+    rows = []
+    for q in range(EVAL_PROBLEMS):
+        pr = lt.decay_problem(EVAL_N, 10**6 + q, leaf, DEV, ws=ws, e=e)
+        rows += lt.compare(p, [pr], [EVAL_TARGET])
+        del pr
+    for r in rows:
+        assert r["tau"] == r["tau_seeded"], r
+        assert r["err"] <= EVAL_TARGET and r["err_seeded"] <= EVAL_TARGET, r
+    scratch = float(np.mean([r["evals_scratch"] for r in rows]))
+    seeded = float(np.mean([r["evals_seeded"] for r in rows]))
+    med = float(np.median([abs(r["log10_ratio_pred"]) for r in rows]))
+    print(f"N={EVAL_N} target {EVAL_TARGET:g}, {len(rows)} problems: evaluations {scratch:.2f} from scratch, "
+          f"{seeded:.2f} seeded; median |log10 tau_pred / tau| {med:.3f}; prediction alone meets the target in "
+          f"{sum(r['pred_meets_target'] for r in rows)}", flush=True)
+    assert seeded < scratch

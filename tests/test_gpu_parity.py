@@ -535,3 +535,103 @@ def test_one_call_without_a_pair_counter(n, leaf):
         assert st == 0
         torch.cuda.synchronize()
         assert torch.equal(c, c_ref)
+
+
+# --------------------------------------------------------------------------
+# leaf 16 (one wave per output tile, 16x16x4 MFMA)
+
+
+@pytest.mark.parametrize(
+    "n,kind,tau",
+    [(1024, "c1", 1e-6), (1000, "exp", 1e-6), (1001, "uni", 0.0), (300, "exp", math.inf), (5, "uni", 0.0),
+     (17, "uni", 1.0), (2048, "alg", 1e-4), (513, "alg", 1e-3)],
+)
+def test_leaf16_matches_oracle(n, kind, tau):
+    """Leaf 16 through spamm_multiply: ragged N (a partial last tile), N below
+    the leaf, tau = 0 (every pair kept), tau = inf (C = 0), the N = 1024
+    exponential-decay inputs at leaf 16: pairs equal the oracle's count, C
+    within the FP32 accumulation bound."""
+    if kind == "c1":
+        a, b = inputs.workload_exp1024()
+    elif kind == "exp":
+        a, b = inputs.exp_decay(n, 0.05, 3), inputs.exp_decay(n, 0.08, 4)
+    elif kind == "alg":
+        a, b = inputs.algebraic_decay_signed(n, 5), inputs.algebraic_decay_signed(n, 6)
+    else:
+        a, b = inputs.uniform_pm1(n, 7), inputs.uniform_pm1(n, 8)
+    c_ref, count, _ = oracle.spamm(a, b, tau, 16)
+    c, pairs = sp.multiply(gpu(a), gpu(b), tau, 16)
+    assert pairs == count
+    if math.isinf(tau):
+        assert pairs == 0 and int(torch.count_nonzero(c)) == 0
+    check_c(c.cpu().numpy(), a, b, tau, 16, c_ref=c_ref)
+
+
+def test_leaf16_staged_calls_equal_one_call():
+    n, leaf, tau = 777, 16, 1e-5
+    a, b = gpu(inputs.exp_decay(n, 0.03, 1)), gpu(inputs.exp_decay(n, 0.03, 2))
+    c1, p1 = sp.multiply(a, b, tau, leaf)
+    offsets, klist, pairs = sp.prepare(a, b, tau, leaf)
+    c2 = sp.execute(a, b, leaf, offsets, klist)
+    assert int(pairs.item()) == p1 and torch.equal(c1, c2)
+
+
+# --------------------------------------------------------------------------
+# a NULL workspace: the library's cached per-device workspace, spamm_release
+
+
+def test_null_workspace_equals_caller_workspace_and_release():
+    cases = [(1024, 32, 1e-6), (2000, 64, 1e-5), (777, 128, 1e-6), (300, 16, 1e-6)]
+    for n, leaf, tau in cases:  # growing and shrinking requests on one device
+        a, b = gpu(inputs.exp_decay(n, 0.05, 11)), gpu(inputs.exp_decay(n, 0.05, 12))
+        c_own, p_own = sp.multiply(a, b, tau, leaf)
+        c_lib, p_lib = sp.multiply(a, b, tau, leaf, ws=sp.LIBRARY_WORKSPACE)
+        assert p_own == p_lib and torch.equal(c_own, c_lib), (n, leaf)
+    sp.release()
+    sp.release()  # nothing cached: a no-op
+    n, leaf, tau = 512, 32, 1e-4
+    a, b = gpu(inputs.exp_decay(n, 0.05, 13)), gpu(inputs.exp_decay(n, 0.05, 14))
+    c_own, p_own = sp.multiply(a, b, tau, leaf)
+    c_lib, p_lib = sp.multiply(a, b, tau, leaf, ws=sp.LIBRARY_WORKSPACE)  # allocates again
+    assert p_own == p_lib and torch.equal(c_own, c_lib)
+    sp.release()
+
+
+# --------------------------------------------------------------------------
+# the plan and the multiply schedule from one launch (spamm_prepare_schedule)
+
+
+@pytest.mark.parametrize(
+    "n,leaf,tau,kind",
+    [(1000, 64, 1e-6, "exp"), (8192, 64, 1e-6, "alg"), (4160, 32, 1e-5, "exp"), (2080, 32, 0.0, "uni"),
+     (300, 32, math.inf, "exp"), (64, 64, 0.0, "uni"), (70, 64, 1e-3, "uni"), (6400, 64, 1e-4, "alg"),
+     (3000, 32, 1e-6, "alg")],
+)
+def test_fused_plan_equals_staged_plan(n, leaf, tau, kind):
+    """Offsets, k-lists and pairs of spamm_prepare_schedule equal those of
+    spamm_prepare bitwise (odd and even tile grids, one or several 64-tile
+    column blocks, tau = 0 and inf), and the multiply after each gives
+    bitwise the same C; a second call on the same workspace gives the same
+    again (the look-back state is cleared by every call)."""
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.05, 1), inputs.exp_decay(n, 0.03, 2)
+    elif kind == "alg":
+        a, b = inputs.algebraic_decay_signed(n, 0), inputs.algebraic_decay_signed(n, 1)
+    else:
+        a, b = inputs.uniform_pm1(n, 3), inputs.uniform_pm1(n, 4)
+    ga, gb = gpu(a), gpu(b)
+    ws1 = sp.workspace(n, leaf, DEV).clone()
+    ws2 = sp.workspace(n, leaf, DEV).clone()
+    o1, k1, p1 = sp.prepare(ga, gb, tau, leaf, ws=ws1)
+    c1 = sp.execute(ga, gb, leaf, o1, k1, ws=ws1)
+    bd = sp.bdim(n, leaf)
+    for rep in range(2):
+        o2, k2, p2 = sp.prepare(ga, gb, tau, leaf, ws=ws2, schedule=True)
+        c2 = sp.execute_scheduled(ga, gb, leaf, o2, k2, ws=ws2)
+        total = int(p1.item())
+        assert int(p2.item()) == total, rep
+        assert torch.equal(o1[: bd * bd + 1], o2[: bd * bd + 1]), rep
+        assert torch.equal(k1[:total], k2[:total]), rep
+        assert torch.equal(c1, c2), rep
+    if n == 8192:
+        assert total == closed_form_pair_count(n, leaf, tau)[0]
