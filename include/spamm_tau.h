@@ -40,9 +40,12 @@ int64_t spamm_mlp_param_count(void);
 int64_t spamm_mlp_acts_floats(int32_t batch);
 
 /* Features of one (A, B, target) problem, FP32 [129]: for A then B, 64 bins
- * of log10(leaf norm) over [-46, 3) in steps of 49/64, each the fraction of
- * the bdim^2 leaf tiles that fall in it (a zero norm counts in bin 0, a norm
- * below or above the range in the first or last bin); then log10(target).
+ * of log10(leaf norm) over [-46, 3) in steps of 49/64, each the number of
+ * leaf tiles with a positive norm in it per tile row (count / bdim, so that a
+ * band of the same decay gives the same features at any N), capped at 4 (the
+ * bins of tiny far-off-diagonal norms grow with N); a norm below or above the
+ * range counts in the first or last bin, a zero norm in none; then
+ * log10(target).
  *   pyr_a, pyr_b  pyramids from spamm_pyramid (device).
  *   features      device FP32 [129].
  * EINVAL: null pointer, bad size, target not > 0. */

@@ -3,10 +3,13 @@
 Only the test suite may import this module.  It states, in plain numpy FP64, what
 the learned-threshold path computes:
 
-* features: for A and for B, a 64-bin histogram of log10 of the leaf-tile
-  Frobenius norms (Eq. 2) over the fixed range [-46, 3), normalised by the
-  number of tiles; a zero norm counts in bin 0, norms outside the range in the
-  first or last bin; then log10 of the requested relative error.  129 numbers.
+* features: for A and for B, a 64-bin histogram of log10 of the positive
+  leaf-tile Frobenius norms (Eq. 2) over the fixed range [-46, 3) (norms
+  outside the range in the first or last bin; zero norms are not counted),
+  each bin as tiles per tile row (count / bdim) capped at 4; then log10 of the
+  requested relative error.  129 numbers.  Per tile row, a band of the same
+  decay gives the same features at any N; the cap bounds the bins of tiny
+  far-off-diagonal norms, which grow with N.
 * the network: 129 -> 128 -> 128 -> 1, GELU (erf form) after both hidden
   layers, output log10(tau).  Parameters flat in this order: W1 [128, 129]
   (row = output unit), b1 [128], W2 [128, 128], b2 [128], w3 [128], b3 [1].
@@ -33,6 +36,7 @@ from . import leaf_norms, spamm
 N_BINS = 64
 LOG_LO = -46.0
 LOG_HI = 3.0
+HIST_CAP = 4.0
 N_IN = 2 * N_BINS + 1
 N_HID = 128
 
@@ -61,16 +65,16 @@ def pack(p: dict) -> np.ndarray:
 # features
 
 
-def histogram(norms) -> np.ndarray:
-    """64-bin histogram of log10(norm) over [LOG_LO, LOG_HI), normalised."""
+def histogram(norms, rows: int) -> np.ndarray:
+    """64-bin histogram of log10 of the positive norms over [LOG_LO, LOG_HI),
+    as counts per row of the tile grid (rows = bdim), capped at HIST_CAP."""
     x = np.asarray(norms, dtype=np.float64).ravel()
     bins = np.zeros(N_BINS, dtype=np.int64)
     pos = x > 0
     t = (np.log10(x[pos]) - LOG_LO) * (N_BINS / (LOG_HI - LOG_LO))
     idx = np.clip(np.floor(t), 0, N_BINS - 1).astype(np.int64)
     np.add.at(bins, idx, 1)
-    bins[0] += int(np.count_nonzero(~pos))
-    return bins / max(1, x.size)
+    return np.minimum(bins / float(rows), HIST_CAP)
 
 
 def bin_position(norms) -> np.ndarray:
@@ -81,8 +85,8 @@ def bin_position(norms) -> np.ndarray:
 
 
 def features(a, b, leaf: int, target: float) -> np.ndarray:
-    return np.concatenate([histogram(leaf_norms(a, leaf)), histogram(leaf_norms(b, leaf)),
-                           [math.log10(target)]])
+    na, nb = leaf_norms(a, leaf), leaf_norms(b, leaf)
+    return np.concatenate([histogram(na, na.shape[0]), histogram(nb, nb.shape[0]), [math.log10(target)]])
 
 
 # --------------------------------------------------------------------------

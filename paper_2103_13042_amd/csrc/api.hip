@@ -241,7 +241,7 @@ spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, doub
     double* pb = at<double>(ws, L.pyr[1]);
     const float* xs[2] = {a, b};
     double* ps[2] = {pa, pb};
-    const bool fused = schedule && (g.leaf == 32 || g.leaf == 64);
+    const bool fused = schedule && (g.leaf == 32 || g.leaf == 64) && g.bdim <= spamm::kPlanMacroMaxBdim;
     int64_t* state = at<int64_t>(ws, L.pm_state);
     spamm_status st = enqueue_pyramids(g, xs, 2, ps, ws, s, fused ? state : nullptr,
                                        fused ? spamm::plan_macro_clear_words(g.bdim) : 0);
@@ -252,7 +252,6 @@ spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, doub
     }
     const spamm::MacroSchedule ms = macro_schedule(L, ws);
     spamm::PlanMacroOut o{};
-    o.masks = at<uint64_t>(ws, L.masks);
     o.offsets = offsets;
     o.klist = klist;
     o.pairs = pairs;

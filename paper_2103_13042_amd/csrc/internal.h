@@ -57,13 +57,13 @@ hipError_t launch_plan_fill(const uint64_t* masks, const int32_t* counts, const 
                             int64_t bdim, int32_t* offsets, int32_t* klist, hipStream_t s);
 
 // Plan and macro-tile schedule in one launch (plan_macro.hip; leaf 32 and 64,
-// bdim <= 1024): the outputs of launch_plan_mask + launch_plan_scan +
-// launch_plan_fill (offsets, klist, pairs) and of launch_macro_schedule
-// (uprefix, items); masks is scratch of bdim * bdim * nwords words; flags
-// (mb words, mb = ceil(bdim / 2)) and the ticket after them must be zero
-// before the launch (kPlanMacroClearWords words from flags).
+// bdim <= kPlanMacroMaxBdim): the outputs of launch_plan_mask +
+// launch_plan_scan + launch_plan_fill (offsets, klist, pairs) and of
+// launch_macro_schedule (uprefix, items); flags (mb words, mb = ceil(bdim /
+// 2)) and the ticket after them must be zero before the launch
+// (plan_macro_clear_words(bdim) words from flags).
+constexpr int64_t kPlanMacroMaxBdim = 256;
 struct PlanMacroOut {
-    uint64_t* masks;
     int32_t* offsets;
     int32_t* klist;
     int64_t* pairs;  // may be null

@@ -13,12 +13,14 @@
 namespace spamm {
 
 // --------------------------------------------------------------------------
-// Features: per matrix a 64-bin histogram of log10 of the leaf norms over
-// [-46, 3), normalised by the number of real tiles; zero norms count in bin 0,
-// norms outside the range in the first or last bin.  Then log10(target).
+// Features: per matrix a 64-bin histogram of log10 of the positive leaf norms
+// over [-46, 3) (norms outside the range in the first or last bin), as tiles
+// per tile row (count / bdim) capped at kHistCap; zero norms are not
+// counted.  Then log10(target).
 
 constexpr int kHistBins = 64;
 constexpr double kLogLo = -46.0, kLogHi = 3.0;
+constexpr double kHistCap = 4.0;
 constexpr int kFeatThreads = 1024;
 
 __global__ __launch_bounds__(kFeatThreads) void tau_features_kernel(const double* __restrict__ pyr_a,
@@ -34,18 +36,19 @@ __global__ __launch_bounds__(kFeatThreads) void tau_features_kernel(const double
         const double* leaf = (m == 0 ? pyr_a : pyr_b) + level_offset(lv);
         for (int64_t t = threadIdx.x; t < tiles; t += kFeatThreads) {
             const double x = leaf[(t / bdim) * side + t % bdim];
-            int bin = 0;
             if (x > 0.0) {
                 const double pos = (log10(x) - kLogLo) * (double(kHistBins) / (kLogHi - kLogLo));
                 const double f = floor(pos);
-                bin = f < 0.0 ? 0 : (f > kHistBins - 1 ? kHistBins - 1 : int(f));
+                const int bin = f < 0.0 ? 0 : (f > kHistBins - 1 ? kHistBins - 1 : int(f));
+                atomicAdd(&hist[m][bin], 1);
             }
-            atomicAdd(&hist[m][bin], 1);
         }
     }
     __syncthreads();
-    if (threadIdx.x < 2 * kHistBins)
-        out[threadIdx.x] = float(double(hist[threadIdx.x / kHistBins][threadIdx.x % kHistBins]) / double(tiles));
+    if (threadIdx.x < 2 * kHistBins) {
+        const double per_row = double(hist[threadIdx.x / kHistBins][threadIdx.x % kHistBins]) / double(bdim);
+        out[threadIdx.x] = float(per_row < kHistCap ? per_row : kHistCap);
+    }
     if (threadIdx.x == 0) out[2 * kHistBins] = log_target;
 }
 

@@ -6,13 +6,15 @@
 // output tiles that the multiply streams, section 3.5.1's balanced work
 // split reads their prefix), with identical outputs.
 //
-// One workgroup per macro-tile row I (output tile rows 2I and 2I+1), taken in
-// order of a ticket so that every lower row's workgroup has started:
+// One workgroup of sixteen waves per macro-tile row I (output tile rows 2I
+// and 2I+1), taken in order of a ticket so that every lower row's workgroup
+// has started; grids of up to 256 tiles per side, so that the row pair's
+// bitmaps stay in LDS:
 //  1. the tests: per k-chunk of 64 (one pyramid node of 64 x 64 leaf tiles on
 //     each side settles the chunk for 64 tile columns when its product is
 //     below tau), B's leaf norms staged in LDS, one ballot per (tile, chunk)
-//     gives the bitmap of kept k; per tile the count V, per macro tile the
-//     size of the union of its four bitmaps;
+//     gives the bitmap of kept k (kept in LDS); per tile the count V, per
+//     macro tile the size of the union of its four bitmaps;
 //  2. the row's two sums (kept pairs, union entries) are combined with those
 //     of the rows before it by a decoupled look-back: each row publishes its
 //     sums, then its inclusive prefix, in one 64-bit word per row written and
@@ -32,9 +34,9 @@
 namespace spamm {
 
 namespace {
-constexpr int kPmThreads = 256;
+constexpr int kPmThreads = 1024;
 constexpr int kPmWaves = kPmThreads / 64;
-constexpr int64_t kPmMaxBdim = 1024;
+constexpr int64_t kPmMaxBdim = kPlanMacroMaxBdim;
 constexpr int kPmMaxNw = int(kPmMaxBdim / 64);
 constexpr uint32_t kPmMaxSpins = 1u << 22;
 
@@ -59,10 +61,10 @@ __device__ __forceinline__ void atomic_store_agent(unsigned long long* p, unsign
 __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __restrict__ pyr_a,
                                                                 const double* __restrict__ pyr_b, int64_t bdim,
                                                                 int lv, double tau, PlanMacroOut o) {
-    __shared__ double sb[64][65];                    // B leaf norms of a chunk: [k][j]
-    __shared__ int32_t tcount[2][kPmMaxBdim];        // V of the row pair's tiles
-    __shared__ int32_t ucnt[kPmMaxBdim / 2];         // union sizes of the row's macro tiles
-    __shared__ uint32_t skip[kPmMaxNw];              // bit c of word jb: chunk c settled as empty
+    __shared__ double sb[64][65];                         // B leaf norms of a chunk: [k][j]
+    __shared__ uint64_t smask[2][kPmMaxBdim][kPmMaxNw];   // bitmaps of the row pair's tiles
+    __shared__ int32_t tcount[2][kPmMaxBdim];             // V of the row pair's tiles
+    __shared__ int32_t ucnt[kPmMaxBdim / 2];              // union sizes of the row's macro tiles
     __shared__ int64_t wsum[2][kPmWaves];
     __shared__ unsigned long long s_excl;
     __shared__ int64_t s_row;
@@ -81,16 +83,14 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
 
     // ---- 1. tests, bitmaps, counts
     for (int64_t jb = 0; jb < nw; ++jb) {
-        // wave w: macro columns J = 32 jb + w + 4 u (u = 0..7) of this column block
-        int cnt[8][4];
-        int uc[8];
+        // wave w: macro columns J = 32 jb + w + 16 u (u = 0, 1) of this column block
+        int cnt[2][4], uc[2];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 2; ++u) {
             uc[u] = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) cnt[u][q] = 0;
         }
-        uint32_t skipbits = 0;
         for (int c = 0; c < nw; ++c) {
             bool below;
             if (lv >= 6) {
@@ -102,12 +102,16 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
                 below = !(pyr_a[0] * pyr_b[0] >= tau);
             }
             if (below) {  // no triple of the chunk is kept, for any tile of the block
-                skipbits |= 1u << c;
+                if (tid < 128) {
+                    const int h = tid >> 6;
+                    const int64_t j = jb * 64 + (tid & 63);
+                    if (j < bdim) smask[h][j][c] = 0ull;
+                }
                 continue;
             }
-            double v[16];
+            double v[4];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 const int e = tid + u * kPmThreads;
                 const int64_t k = int64_t(c) * 64 + (e >> 6), j = jb * 64 + (e & 63);
                 v[u] = (k < side && j < side) ? lb[k * side + j] : 0.0;
@@ -115,16 +119,16 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
             const int64_t k = int64_t(c) * 64 + lane;
             const double a0 = k < side ? la[r0 * side + k] : 0.0;
             const double a1 = (k < side && r0 + 1 < side) ? la[(r0 + 1) * side + k] : 0.0;
-            __syncthreads();
+            __syncthreads();  // every wave is done with the previous chunk's norms
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 const int e = tid + u * kPmThreads;
                 sb[e >> 6][e & 63] = v[u];
             }
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int jj = 2 * (wave + 4 * u);  // first tile column of macro column J, in the block
+            for (int u = 0; u < 2; ++u) {
+                const int jj = 2 * (wave + 16 * u);  // first tile column of the macro column, in the block
                 uint64_t uni = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -132,18 +136,17 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
                     const int64_t r = r0 + h, j = jb * 64 + jj + bcol;
                     const double p = (h ? a1 : a0) * sb[lane][jj + bcol];
                     const uint64_t mk = __ballot(p >= tau && k < bdim && r < bdim && j < bdim);
-                    if (lane == 0 && r < bdim && j < bdim) o.masks[(r * bdim + j) * nw + c] = mk;
+                    if (lane == 0 && j < bdim) smask[h][j][c] = mk;
                     cnt[u][q] += __popcll(mk);
                     uni |= mk;
                 }
                 uc[u] += __popcll(uni);
             }
         }
-        if (tid == 0) skip[jb] = skipbits;
+        if (lane == 0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t J = jb * 32 + wave + 4 * u;
-            if (lane == 0) {
+            for (int u = 0; u < 2; ++u) {
+                const int64_t J = jb * 32 + wave + 16 * u;
                 if (J < mb) ucnt[J] = uc[u];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -195,9 +198,9 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
         bool timed_out = false;
         while (top >= 0) {
             const int64_t p = top - lane;
-            unsigned long long wv = p >= 0 ? atomic_load_agent(o.flags + p) : kStIncl;
-            uint64_t incl = __ballot((wv >> 62) == 2);
-            uint64_t ready = __ballot((wv >> 62) != 0);
+            const unsigned long long wv = p >= 0 ? atomic_load_agent(o.flags + p) : kStIncl;
+            const uint64_t incl = __ballot((wv >> 62) == 2);
+            const uint64_t ready = __ballot((wv >> 62) != 0);
             // lanes up to and including the first inclusive one must all be ready
             const int first = incl ? __ffsll((unsigned long long)incl) - 1 : 63;
             const uint64_t need = first == 63 ? ~0ull : ((2ull << first) - 1);
@@ -268,10 +271,8 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
         const int64_t t = r * bdim + j;
         int64_t base = base_p + (h ? wsum[0][0] : 0) + tcount[h][j];
         if (lane == 0) o.offsets[t] = int32_t(base);
-        const uint32_t sk = skip[j >> 6];
         for (int c = 0; c < nw; ++c) {
-            if ((sk >> c) & 1u) continue;
-            const uint64_t m = o.masks[t * nw + c];
+            const uint64_t m = smask[h][j][c];
             if ((m >> lane) & 1ull) o.klist[base + __popcll(m & below_mask)] = c * 64 + lane;
             base += __popcll(m);
         }
@@ -282,14 +283,12 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
         const int64_t m = I * mb + J;
         int64_t base = base_u + ucnt[J];
         if (lane == 0) o.uprefix[m] = int32_t(base);
-        const uint32_t sk = skip[(2 * J) >> 6];
         for (int c = 0; c < nw; ++c) {
-            if ((sk >> c) & 1u) continue;
             uint64_t w4[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = r0 + (q >> 1), j = 2 * J + (q & 1);
-                w4[q] = (r < bdim && j < bdim) ? o.masks[(r * bdim + j) * nw + c] : 0ull;
+                w4[q] = (r < bdim && j < bdim) ? smask[q >> 1][j][c] : 0ull;
             }
             const uint64_t u = w4[0] | w4[1] | w4[2] | w4[3];
             if ((u >> lane) & 1ull) {

@@ -40,28 +40,42 @@ def test_parameter_count_and_layout():
     assert np.array_equal(learned.pack(p), flat)
 
 
-def _hist_brute(norms):
+def _hist_brute(norms, rows):
     counts = [0] * 64
     for v in np.asarray(norms, dtype=np.float64).ravel().tolist():
         if v <= 0.0:
-            counts[0] += 1
-            continue
+            continue  # zero norms are not counted
         t = (math.log10(v) + 46.0) * 64.0 / 49.0
         counts[min(63, max(0, math.floor(t)))] += 1
-    tot = sum(counts)
-    return [c / tot for c in counts]
+    return [min(c / rows, 4.0) for c in counts]
 
 
 def test_histogram_brute_force():
     rng = np.random.default_rng(3)
     vals = np.concatenate([10.0 ** rng.uniform(-50, 6, size=500), [0.0, 0.0, 1e-300, 5e3, 1.0]])
-    h = learned.histogram(vals)
-    assert np.allclose(h, _hist_brute(vals), rtol=0, atol=1e-15)
-    assert h.sum() == pytest.approx(1.0, abs=1e-14)
+    h = learned.histogram(vals, 100)
+    assert np.allclose(h, _hist_brute(vals, 100), rtol=0, atol=1e-15)
+    assert h.sum() == pytest.approx(503 / 100, abs=1e-12)  # the positive values, per row, none capped
+    assert np.allclose(learned.histogram(vals, 2), _hist_brute(vals, 2), rtol=0, atol=1e-15)
+    assert learned.histogram(vals, 2).max() == 4.0  # capped
     # leaf norms of an actual decay matrix
     a = inputs.exp_decay(256, 0.3, 5)
-    assert np.allclose(learned.histogram(oracle.leaf_norms(a, 16)), _hist_brute(oracle.leaf_norms(a, 16)),
-                       rtol=0, atol=1e-15)
+    na = oracle.leaf_norms(a, 16)
+    assert np.allclose(learned.histogram(na, 16), _hist_brute(na, 16), rtol=0, atol=1e-15)
+
+
+def test_histogram_is_size_invariant_for_a_band():
+    # a matrix that is a pure band (|i-j| < 2.5 tiles, equal values): the
+    # histogram per tile row only moves by the band's truncated rows at the
+    # edges, which shrink like 1/bdim
+    def band(n):
+        i = np.arange(n)
+        return (np.abs(i[:, None] - i[None, :]) < 2 * 32 + 16).astype(np.float32)
+
+    h1 = learned.histogram(oracle.leaf_norms(band(1024), 32), 32)
+    h2 = learned.histogram(oracle.leaf_norms(band(4096), 32), 128)
+    assert np.count_nonzero(h1) == np.count_nonzero(h2) >= 1
+    assert np.allclose(h1, h2, rtol=0, atol=5.0 / 32)
 
 
 def _forward_brute(flat, x):
