@@ -199,30 +199,45 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     };
 
     // copies of item (pair item pi, chunk ch) into stage st: KC/32 A and KC/32
-    // B instructions of 1 KiB per wave
+    // B instructions of 1 KiB per wave.  A is staged as 128 rows of KC; B as
+    // two column halves (one per output tile column), each KC rows of 64.
+    // Waves 0-7 copy the first half of each operand (A rows of output tile row
+    // 0, B columns of tile column 0), waves 8-15 the second; a half that no
+    // tile keeping the item's k reads is not copied (the membership bits tell),
+    // so an item kept by one tile moves half the bytes.  The copy waits count
+    // only the stores issued after a wave's copies, which holds for any number
+    // of copies per wave with two stages.
+    static_assert(kDmaStages == 2, "copies per wave vary with the item");
     constexpr int ACH = KC / 4;  // 16-byte chunks per A row
+    constexpr int BHALF = KC * LEAF * 4;  // bytes of one B column half
     auto aswz = [](int r) { return KC == 32 ? ((r >> 1) & 7) : (r & 15); };
+    const int half = wave >> 3;
+    const uint32_t need_a = half ? 12u : 3u, need_b = half ? 10u : 5u;
     auto copy_item = [&](uint32_t pi, int ch, int st) {
         const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
         char* sbase = lds + st * STAGE_BYTES;
+        if (pi & need_a) {
 #pragma unroll
-        for (int j = 0; j < KC / 32; ++j) {  // A: 1024 / (4 KC) rows per instruction
-            const int blk = wave * (KC / 32) + j;
-            const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
-            const int c = p ^ aswz(r);
-            const float* src = A + (2 * I * LEAF + r) * n + kt * LEAF + ch * KC + 4 * c;
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sbase + blk * 1024), 16, 0,
-                                             0);
+            for (int j = 0; j < KC / 32; ++j) {  // A: 1024 / (4 KC) rows per instruction
+                const int blk = wave * (KC / 32) + j;
+                const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
+                const int c = p ^ aswz(r);
+                const float* src = A + (2 * I * LEAF + r) * n + kt * LEAF + ch * KC + 4 * c;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sbase + blk * 1024),
+                                                 16, 0, 0);
+            }
         }
+        if (pi & need_b) {
 #pragma unroll
-        for (int j = 0; j < KC / 32; ++j) {  // B: 2 rows of 32 chunks per instruction
-            const int blk = wave * (KC / 32) + j;
-            const int r = blk * 2 + (lane >> 5), p = lane & 31;
-            const int c = p ^ (8 * ((r / SPC) & 1));
-            const float* src = B + (kt * LEAF + ch * KC + r) * n + 2 * J * LEAF + 4 * c;
-            __builtin_amdgcn_global_load_lds(src,
-                                             (__attribute__((address_space(3))) void*)(sbase + ABYTES + blk * 1024),
-                                             16, 0, 0);
+            for (int j = 0; j < KC / 32; ++j) {  // B: 4 rows of 16 chunks of one half per instruction
+                const int blk = (wave & 7) * (KC / 32) + j;
+                const int r = blk * 4 + (lane >> 4), p = lane & 15;
+                const int c = p ^ (8 * ((r / SPC) & 1));
+                const float* src = B + (kt * LEAF + ch * KC + r) * n + 2 * J * LEAF + half * LEAF + 4 * c;
+                __builtin_amdgcn_global_load_lds(
+                    src, (__attribute__((address_space(3))) void*)(sbase + ABYTES + half * BHALF + blk * 1024), 16, 0,
+                    0);
+            }
         }
     };
     // operands are read in groups of GRP MFMA steps, one group ahead of the
@@ -233,8 +248,8 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
         const char* sa = lds + st * STAGE_BYTES;
         const char* sb = sa + ABYTES;
         const int r = wa * 64 + qr * 32 + ir;
-        const int cc = wb * 64 + qc * 32 + ir;
-        const char* brow = sb + ((cc >> 2) ^ (8 * g)) * 16 + (cc & 3) * 4;
+        const int cc = qc * 32 + ir;  // column within tile column wb's half of B
+        const char* brow = sb + wb * BHALF + ((cc >> 2) ^ (8 * g)) * 16 + (cc & 3) * 4;
         f4 av[2][GRP / 4];
         float bv[2][GRP];
         auto load = [&](int grp, int buf) {
@@ -246,7 +261,7 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
 #pragma unroll
             for (int u = 0; u < GRP; ++u) {
                 const int kr = g * SPC + grp * GRP + u;
-                bv[buf][u] = *reinterpret_cast<const float*>(brow + kr * (2 * LEAF * 4));
+                bv[buf][u] = *reinterpret_cast<const float*>(brow + kr * (LEAF * 4));
             }
         };
         load(0, 0);
