@@ -90,13 +90,13 @@ __global__ __launch_bounds__(kMacThreads, MacGeom<LEAF>::OCC) void multiply_macr
 // LDS rows are stored without padding; 16-byte chunks are XOR-swizzled so the
 // MFMA operand reads are free of bank conflicts.
 //
-// Completion of the copies is tracked by hand with s_waitcnt vmcnt: every
-// wave issues exactly kDmaCopies copies per item and exactly kDmaStores
-// stores per finished macro tile (no access is predicated), so the number of
-// memory operations issued after the copies of item it is known; a split
-// macro tile (below) waits for all of the wave's operations instead.  Empty
-// asm statements with a memory clobber keep the compiler from moving LDS or
-// global accesses across the hand-placed waits and the barrier.
+// Completion of the copies is tracked by hand with s_waitcnt vmcnt: with two
+// stages, a wave's vector-memory operations issued after its copies of item
+// it are exactly the kDmaStores stores of each macro tile it finished since
+// (shared tiles included: their partial sums are stored the same way), so
+// the wait counts those stores whatever number of copies the item needed.
+// Empty asm statements with a memory clobber keep the compiler from moving
+// LDS or global accesses across the hand-placed waits and the barrier.
 //
 // Work split: workgroup g takes the items between boundaries g and g+1 of the
 // item-level cost partition (split_bound), so a macro tile may be shared by

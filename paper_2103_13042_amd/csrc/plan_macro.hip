@@ -56,6 +56,15 @@ __device__ __forceinline__ unsigned long long atomic_load_agent(const unsigned l
 __device__ __forceinline__ void atomic_store_agent(unsigned long long* p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// A workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for this wave's global loads, so a prefetch stays in flight.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 }  // namespace
 
 __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __restrict__ pyr_a,
@@ -68,6 +77,7 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
     __shared__ int64_t wsum[2][kPmWaves];
     __shared__ unsigned long long s_excl;
     __shared__ int64_t s_row;
+    __shared__ uint32_t s_settled;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_row = atomicAdd(o.ticket, 1u);
@@ -82,6 +92,51 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
     const int64_t r0 = 2 * I;  // tile rows r0 and r0 + 1 (the latter may lie outside the grid)
 
     // ---- 1. tests, bitmaps, counts
+    // The node tests of every (column block jb, k-chunk c) first, one lane
+    // each (bit jb * nw + c of `settled`: no triple of that chunk is kept for
+    // any tile of the block); then the chunks that remain, the norms of the
+    // next one loaded while this one is tested.
+    if (wave == 0) {
+        bool below = false;
+        if (lane < nw * nw) {
+            const int jb = lane / nw, c = lane - (lane / nw) * nw;
+            if (lv >= 6) {
+                const int lc = lv - 6;
+                const int64_t w = int64_t(1) << lc;
+                below = !(pyr_a[level_offset(lc) + (r0 >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + jb] >=
+                          tau);
+            } else {
+                below = !(pyr_a[0] * pyr_b[0] >= tau);
+            }
+        }
+        const uint64_t bits = __ballot(below);
+        if (lane == 0) s_settled = uint32_t(bits);
+    }
+    __syncthreads();
+    const uint32_t settled = s_settled;
+    const int nit = nw * nw;
+    auto next_open = [&](int from) {
+        int it = from;
+        while (it < nit && ((settled >> it) & 1u)) ++it;
+        return it;
+    };
+    // this thread's four entries of a chunk's B norms, and the A norms of
+    // rows r0 and r0 + 1 at lane's k
+    double vb[4], va[2];
+    auto fetch = [&](int it) {
+        const int64_t jb = it / nw, c = it - (it / nw) * nw;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * kPmThreads;
+            const int64_t k = c * 64 + (e >> 6), j = jb * 64 + (e & 63);
+            vb[u] = (k < side && j < side) ? lb[k * side + j] : 0.0;
+        }
+        const int64_t k = c * 64 + lane;
+        va[0] = k < side ? la[r0 * side + k] : 0.0;
+        va[1] = (k < side && r0 + 1 < side) ? la[(r0 + 1) * side + k] : 0.0;
+    };
+    int open = next_open(0);
+    if (open < nit) fetch(open);
     for (int64_t jb = 0; jb < nw; ++jb) {
         // wave w: macro columns J = 32 jb + w + 16 u (u = 0, 1) of this column block
         int cnt[2][4], uc[2];
@@ -92,16 +147,8 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
             for (int q = 0; q < 4; ++q) cnt[u][q] = 0;
         }
         for (int c = 0; c < nw; ++c) {
-            bool below;
-            if (lv >= 6) {
-                const int lc = lv - 6;
-                const int64_t w = int64_t(1) << lc;
-                below = !(pyr_a[level_offset(lc) + (r0 >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + jb] >=
-                          tau);
-            } else {
-                below = !(pyr_a[0] * pyr_b[0] >= tau);
-            }
-            if (below) {  // no triple of the chunk is kept, for any tile of the block
+            const int it = int(jb) * nw + c;
+            if ((settled >> it) & 1u) {  // no triple of the chunk is kept, for any tile of the block
                 if (tid < 128) {
                     const int h = tid >> 6;
                     const int64_t j = jb * 64 + (tid & 63);
@@ -109,23 +156,17 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
                 }
                 continue;
             }
-            double v[4];
+            const double a0 = va[0], a1 = va[1];
+            lds_barrier();  // every wave is done with the previous chunk's norms
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = tid + u * kPmThreads;
-                const int64_t k = int64_t(c) * 64 + (e >> 6), j = jb * 64 + (e & 63);
-                v[u] = (k < side && j < side) ? lb[k * side + j] : 0.0;
+                sb[e >> 6][e & 63] = vb[u];
             }
+            lds_barrier();
+            open = next_open(it + 1);
+            if (open < nit) fetch(open);  // in flight during this chunk's tests
             const int64_t k = int64_t(c) * 64 + lane;
-            const double a0 = k < side ? la[r0 * side + k] : 0.0;
-            const double a1 = (k < side && r0 + 1 < side) ? la[(r0 + 1) * side + k] : 0.0;
-            __syncthreads();  // every wave is done with the previous chunk's norms
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = tid + u * kPmThreads;
-                sb[e >> 6][e & 63] = v[u];
-            }
-            __syncthreads();
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int jj = 2 * (wave + 16 * u);  // first tile column of the macro column, in the block
@@ -262,41 +303,38 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
         if (wave < 2 && lane == 0) wsum[0][wave] = run;  // the tile row's total
     }
     __syncthreads();
-    const uint64_t below_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // tiles: one wave per tile of rows r0, r0 + 1
-    for (int64_t e = wave; e < 2 * bdim; e += kPmWaves) {
+    // tiles: one thread per (tile of rows r0, r0 + 1, k-chunk); its kept k
+    // in ascending order, after the k of the tile's earlier chunks
+    const int64_t row0_total = wsum[0][0];
+    for (int64_t x = tid; x < 2 * bdim * nw; x += kPmThreads) {
+        const int c = int(x % nw);
+        const int64_t e = x / nw;
         const int h = int(e / bdim);
         const int64_t j = e - h * bdim, r = r0 + h;
-        if (r >= bdim) break;
-        const int64_t t = r * bdim + j;
-        int64_t base = base_p + (h ? wsum[0][0] : 0) + tcount[h][j];
-        if (lane == 0) o.offsets[t] = int32_t(base);
-        for (int c = 0; c < nw; ++c) {
-            const uint64_t m = smask[h][j][c];
-            if ((m >> lane) & 1ull) o.klist[base + __popcll(m & below_mask)] = c * 64 + lane;
-            base += __popcll(m);
-        }
+        if (r >= bdim) continue;
+        int64_t base = base_p + (h ? row0_total : 0) + tcount[h][j];
+        for (int cc = 0; cc < c; ++cc) base += __popcll(smask[h][j][cc]);
+        if (c == 0) o.offsets[r * bdim + j] = int32_t(base);
+        for (uint64_t m = smask[h][j][c]; m; m &= m - 1) o.klist[base++] = c * 64 + __builtin_ctzll(m);
     }
-    // macro tiles: one wave per macro tile of row I; the union of the four
-    // bitmaps, items in ascending k (macro_items_wave's packing)
-    for (int64_t J = wave; J < mb; J += kPmWaves) {
-        const int64_t m = I * mb + J;
+    // macro tiles: one thread per (macro tile of row I, k-chunk); the union of
+    // the four bitmaps in ascending k, packed as macro_items_wave packs them
+    for (int64_t x = tid; x < mb * nw; x += kPmThreads) {
+        const int c = int(x % nw);
+        const int64_t J = x / nw, m = I * mb + J;
+        auto word = [&](int q, int cc) -> uint64_t {
+            const int64_t r = r0 + (q >> 1), j = 2 * J + (q & 1);
+            return (r < bdim && j < bdim) ? smask[q >> 1][j][cc] : 0ull;
+        };
         int64_t base = base_u + ucnt[J];
-        if (lane == 0) o.uprefix[m] = int32_t(base);
-        for (int c = 0; c < nw; ++c) {
-            uint64_t w4[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t r = r0 + (q >> 1), j = 2 * J + (q & 1);
-                w4[q] = (r < bdim && j < bdim) ? smask[q >> 1][j][c] : 0ull;
-            }
-            const uint64_t u = w4[0] | w4[1] | w4[2] | w4[3];
-            if ((u >> lane) & 1ull) {
-                const uint32_t mem = uint32_t((w4[0] >> lane) & 1) | uint32_t(((w4[1] >> lane) & 1) << 1) |
-                                     uint32_t(((w4[2] >> lane) & 1) << 2) | uint32_t(((w4[3] >> lane) & 1) << 3);
-                o.items[base + __popcll(u & below_mask)] = mi_pack(uint32_t(I), uint32_t(J), uint32_t(c * 64 + lane), mem);
-            }
-            base += __popcll(u);
+        for (int cc = 0; cc < c; ++cc) base += __popcll(word(0, cc) | word(1, cc) | word(2, cc) | word(3, cc));
+        if (c == 0) o.uprefix[m] = int32_t(base);
+        const uint64_t w0 = word(0, c), w1 = word(1, c), w2 = word(2, c), w3 = word(3, c);
+        for (uint64_t u = w0 | w1 | w2 | w3; u; u &= u - 1) {
+            const int b = __builtin_ctzll(u);
+            const uint32_t mem = uint32_t((w0 >> b) & 1) | uint32_t(((w1 >> b) & 1) << 1) |
+                                 uint32_t(((w2 >> b) & 1) << 2) | uint32_t(((w3 >> b) & 1) << 3);
+            o.items[base++] = mi_pack(uint32_t(I), uint32_t(J), uint32_t(c * 64 + b), mem);
         }
     }
 }
