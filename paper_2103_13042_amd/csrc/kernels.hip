@@ -668,6 +668,9 @@ constexpr int kRing = 512;  // packed pairs held in LDS (a power of two)
 #ifndef SPAMM_OCC128
 #define SPAMM_OCC128 1
 #endif
+// four floats read with one 16-byte load from a 4-byte aligned address
+typedef float f4_dw __attribute__((ext_vector_type(4), aligned(4)));
+
 template <int LEAF>
 struct MulCfg;
 template <>
@@ -802,7 +805,10 @@ __device__ __forceinline__ void mul_range(const float* __restrict__ A, const flo
     };
 
     // global -> register staging of one (pair, chunk) item; every lane issues
-    // every load (clamped to a valid address) and zeroes what lies outside C
+    // every load (clamped to a valid address) and zeroes what lies outside C.
+    // Rows that are not 16-byte aligned (VEC false) are read with 16-byte
+    // loads at 4-byte alignment, which global loads accept; only chunks that
+    // cross the matrix's edge are read element by element
     auto fetch = [&](int32_t pk, int ch, f4 (&ra)[Gm::NV], f4 (&rb)[Gm::NV]) {
         const int64_t ti = (uint32_t(pk) >> (2 * kIdxBits)) & kIdxMask, tj = (uint32_t(pk) >> kIdxBits) & kIdxMask,
                       kt = uint32_t(pk) & kIdxMask;
@@ -819,6 +825,8 @@ __device__ __forceinline__ void mul_range(const float* __restrict__ A, const flo
                     const bool in = row < n && col < n;
                     const f4 x = *reinterpret_cast<const f4*>(A + (in ? row * n + col : 0));
                     ra[v] = in ? x : zero;
+                } else if (row < n && col + 3 < n) {  // 4-byte aligned: one 16-byte load
+                    ra[v] = *reinterpret_cast<const f4_dw*>(A + row * n + col);
                 } else {
 #pragma unroll
                     for (int q4 = 0; q4 < 4; ++q4) {
@@ -835,6 +843,8 @@ __device__ __forceinline__ void mul_range(const float* __restrict__ A, const flo
                     const bool in = row < n && col < n;
                     const f4 x = *reinterpret_cast<const f4*>(B + (in ? row * n + col : 0));
                     rb[v] = in ? x : zero;
+                } else if (row < n && col + 3 < n) {
+                    rb[v] = *reinterpret_cast<const f4_dw*>(B + row * n + col);
                 } else {
 #pragma unroll
                     for (int q4 = 0; q4 < 4; ++q4) {
