@@ -668,9 +668,6 @@ constexpr int kRing = 512;  // packed pairs held in LDS (a power of two)
 #ifndef SPAMM_OCC128
 #define SPAMM_OCC128 1
 #endif
-// four floats read with one 16-byte load from a 4-byte aligned address
-typedef float f4_dw __attribute__((ext_vector_type(4), aligned(4)));
-
 template <int LEAF>
 struct MulCfg;
 template <>

@@ -74,6 +74,10 @@ __device__ __forceinline__ void macro_items_wave(const uint64_t* __restrict__ wo
     }
 }
 
+// four floats read with one 16-byte load from a 4-byte aligned address
+// (global loads accept it)
+typedef float f4_dw __attribute__((ext_vector_type(4), aligned(4)));
+
 template <int LEAF>
 struct MacGeom {
     static constexpr int KC = 32;                 // k per pipeline stage
@@ -148,6 +152,8 @@ __device__ __forceinline__ void macro_range(const float* __restrict__ A, const f
     // global -> registers for one item (pair item pi, chunk ch): A rows
     // [2I*L, 2I*L + 2L) x k-chunk, B k-chunk x columns [2J*L, 2J*L + 2L).  Every
     // lane issues every load (clamped) and zeroes what lies outside the matrix.
+    // Rows that are not 16-byte aligned (VEC false) take 16-byte loads at
+    // 4-byte alignment; chunks that cross the matrix's edge, one per element.
     auto fetch = [&](uint32_t pi, int ch, f4 (&ra)[Gm::NV], f4 (&rb)[Gm::NV]) {
         const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
         const int64_t arow0 = 2 * I * LEAF, acol0 = kt * LEAF + ch * Gm::KC;
@@ -163,6 +169,8 @@ __device__ __forceinline__ void macro_range(const float* __restrict__ A, const f
                     const bool in = row < n && col < n;
                     const f4 x = *reinterpret_cast<const f4*>(A + (in ? row * n + col : 0));
                     ra[v] = in ? x : zero;
+                } else if (row < n && col + 3 < n) {  // 4-byte aligned: one 16-byte load
+                    ra[v] = *reinterpret_cast<const f4_dw*>(A + row * n + col);
                 } else {
 #pragma unroll
                     for (int q4 = 0; q4 < 4; ++q4) {
@@ -179,6 +187,8 @@ __device__ __forceinline__ void macro_range(const float* __restrict__ A, const f
                     const bool in = row < n && col < n;
                     const f4 x = *reinterpret_cast<const f4*>(B + (in ? row * n + col : 0));
                     rb[v] = in ? x : zero;
+                } else if (row < n && col + 3 < n) {  // 4-byte aligned: one 16-byte load
+                    rb[v] = *reinterpret_cast<const f4_dw*>(B + row * n + col);
                 } else {
 #pragma unroll
                     for (int q4 = 0; q4 < 4; ++q4) {
