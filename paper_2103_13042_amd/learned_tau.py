@@ -190,9 +190,9 @@ def main(argv=None) -> int:
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--eval-n", type=int, default=8192)
-    ap.add_argument("--eval-pairs", type=int, default=6)
+    ap.add_argument("--eval-pairs", type=int, default=32)
     ap.add_argument("--eval-target", type=float, default=1e-4)
-    ap.add_argument("--out", default="gpurun_out/learned")
+    ap.add_argument("--out", default="learned_out", help="folder for the network, the report and the training data")
     args = ap.parse_args(argv)
 
     def log(msg):
