@@ -205,7 +205,7 @@ def main() -> int:
     if args.gpus != 1 or world != 1:
         print(
             f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-            "this SpAMM build measures the single-GPU hot path only",
+            "it measures the single-GPU hot path",
             file=sys.stderr,
         )
         return 2
