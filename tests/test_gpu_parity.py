@@ -206,7 +206,8 @@ def test_multiply_c1_full_parity(c1):
     "n,leaf,q,kind",
     [
         (1000, 64, 0.5, "rand"),   # ragged last tile row/column
-        (1001, 32, 0.3, "rand"),   # N not a multiple of 4: scalar load path
+        (1001, 32, 0.3, "rand"),   # N not a multiple of 4: rows read at 4-byte alignment
+        (1003, 64, 0.5, "exp"),    # the same at leaf 64
         (777, 128, 0.6, "exp"),
         (96, 32, 0.0, "rand"),     # tau = 0: the dense product
         (20, 64, 0.0, "rand"),     # one tile smaller than the leaf
