@@ -196,7 +196,7 @@ spamm_status check_tau(double tau) {
 }
 
 spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
-                              hipStream_t s, int64_t* clear, int64_t clear_count) {
+                              hipStream_t s, int64_t* clear, int64_t clear_count, bool levels) {
     const Layout L = make_layout(g);
     const int64_t leaf_level = spamm::level_offset(g.lv);
     spamm::NormJob nj{};
@@ -214,7 +214,7 @@ spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, do
         vec = vec && aligned16(x[m]);
     }
     spamm_status st = hip_check(spamm::launch_leaf_norms(nj, nmat, g.n, g.leaf, vec, s), "leaf norm kernel");
-    if (st != SPAMM_OK) return st;
+    if (st != SPAMM_OK || !levels) return st;
     return hip_check(spamm::launch_pyramid(pj, nmat, g.bdim, g.lv, s), "pyramid kernel");
 }
 
@@ -242,9 +242,11 @@ spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, doub
     const float* xs[2] = {a, b};
     double* ps[2] = {pa, pb};
     const bool fused = schedule && (g.leaf == 32 || g.leaf == 64) && g.bdim <= spamm::kPlanMacroMaxBdim;
+    // the fused plan needs the pyramid above the leaves only for its node tests
+    const bool node_tests = g.bdim >= spamm::kPlanMacroNodeTestMinBdim;
     int64_t* state = at<int64_t>(ws, L.pm_state);
     spamm_status st = enqueue_pyramids(g, xs, 2, ps, ws, s, fused ? state : nullptr,
-                                       fused ? spamm::plan_macro_clear_words(g.bdim) : 0);
+                                       fused ? spamm::plan_macro_clear_words(g.bdim) : 0, !fused || node_tests);
     if (st != SPAMM_OK) return st;
     if (!fused) {
         if ((st = enqueue_plan(g, pa, pb, tau, false, offsets, klist, pairs, ws, s)) != SPAMM_OK) return st;
@@ -259,7 +261,8 @@ spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, doub
     o.items = ms.items;
     o.flags = reinterpret_cast<unsigned long long*>(state);
     o.ticket = reinterpret_cast<unsigned int*>(state + (g.bdim + 1) / 2);
-    return hip_check(spamm::launch_plan_macro(pa, pb, g.bdim, g.lv, tau, o, s), "plan and schedule kernel");
+    return hip_check(spamm::launch_plan_macro(pa, pb, g.bdim, g.lv, tau, node_tests, o, s),
+                     "plan and schedule kernel");
 }
 
 spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const float* c) {

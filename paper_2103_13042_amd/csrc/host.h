@@ -53,8 +53,9 @@ spamm_status check_mul_args(const Geom& g, const float* a, const float* b, const
 
 // Norm pass and pyramid for nmat matrices whose pyramids go to pyr_out[m];
 // the norm pass also zeroes clear_count int64 words at clear (if not null).
+// levels = false: the leaf level only (the norm pass; no pyramid launch).
 spamm_status enqueue_pyramids(const Geom& g, const float* const* x, int nmat, double* const* pyr_out, void* ws,
-                              hipStream_t s, int64_t* clear = nullptr, int64_t clear_count = 0);
+                              hipStream_t s, int64_t* clear = nullptr, int64_t clear_count = 0, bool levels = true);
 // Norms, pyramids and plan of A and B into the workspace pyramids and the
 // caller's offsets, klist, pairs; with `schedule` (leaf 32 or 64) also the
 // multiply schedule, the plan and schedule then coming from one launch.

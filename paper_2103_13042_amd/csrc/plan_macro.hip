@@ -10,9 +10,11 @@
 // and 2I+1), taken in order of a ticket so that every lower row's workgroup
 // has started; grids of up to 256 tiles per side, so that the row pair's
 // bitmaps stay in LDS:
-//  1. the tests: per k-chunk of 64 (one pyramid node of 64 x 64 leaf tiles on
-//     each side settles the chunk for 64 tile columns when its product is
-//     below tau), B's leaf norms staged in LDS, one ballot per (tile, chunk)
+//  1. the tests: per k-chunk of 64 (with more than 128 tiles per side, one
+//     pyramid node of 64 x 64 leaf tiles on each side settles the chunk for 64
+//     tile columns when its product is below tau; with at most four chunks
+//     every chunk is tested, the pyramid above the leaves then not built),
+//     B's leaf norms staged in LDS, one ballot per (tile, chunk)
 //     gives the bitmap of kept k (kept in LDS); per tile the count V, per
 //     macro tile the size of the union of its four bitmaps;
 //  2. the row's two sums (kept pairs, union entries) are combined with those
@@ -69,7 +71,8 @@ __device__ __forceinline__ void lds_barrier() {
 
 __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __restrict__ pyr_a,
                                                                 const double* __restrict__ pyr_b, int64_t bdim,
-                                                                int lv, double tau, PlanMacroOut o) {
+                                                                int lv, double tau, int node_tests,
+                                                                PlanMacroOut o) {
     __shared__ double sb[64][65];                         // B leaf norms of a chunk: [k][j]
     __shared__ uint64_t smask[2][kPmMaxBdim][kPmMaxNw];   // bitmaps of the row pair's tiles
     __shared__ int32_t tcount[2][kPmMaxBdim];             // V of the row pair's tiles
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
     // next one loaded while this one is tested.
     if (wave == 0) {
         bool below = false;
-        if (lane < nw * nw) {
+        if (node_tests && lane < nw * nw) {
             const int jb = lane / nw, c = lane - (lane / nw) * nw;
             if (lv >= 6) {
                 const int lc = lv - 6;
@@ -340,10 +343,10 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
 }
 
 hipError_t launch_plan_macro(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
-                             const PlanMacroOut& o, hipStream_t s) {
+                             bool node_tests, const PlanMacroOut& o, hipStream_t s) {
     if (bdim < 1 || bdim > kPmMaxBdim) return hipErrorInvalidValue;
     const int64_t mb = (bdim + 1) / 2;
-    plan_macro_kernel<<<unsigned(mb), kPmThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, o);
+    plan_macro_kernel<<<unsigned(mb), kPmThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, node_tests ? 1 : 0, o);
     return hipGetLastError();
 }
 
