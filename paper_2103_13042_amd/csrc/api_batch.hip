@@ -24,7 +24,8 @@ struct BatchPlan {
     size_t header = 0, total = 0;
     std::vector<size_t> base;  // per product region offset
     std::vector<Geom> geom;
-    int64_t tiles = 0, mask_blocks = 0, strips = 0, macros = 0;
+    int64_t tiles = 0, mask_blocks = 0, strips = 0, macros = 0;  // tiles, mask_blocks: products with nwords > 1
+    int32_t small_count = 0;                                     // products with nwords = 1
     int32_t class_count[spamm::kBatchClasses] = {0, 0, 0};
 };
 
@@ -61,8 +62,12 @@ spamm_status plan_batch(int32_t count, const int64_t* n, const int32_t* leaf, Ba
                         SPAMM_MAX_BDIM);
         bp->base[size_t(p)] = o;
         o += product_bytes(g);
-        bp->tiles += g.ntiles;
-        bp->mask_blocks += g.bdim * g.nwords;
+        if (g.nwords > 1) {
+            bp->tiles += g.ntiles;
+            bp->mask_blocks += g.bdim * g.nwords;
+        } else {
+            ++bp->small_count;
+        }
         bp->strips += g.bdim * ((g.n + kNormCols - 1) / kNormCols);
         bp->macros += macro_side(g) * macro_side(g);
         ++bp->class_count[leaf_class(leaf[p])];
@@ -146,8 +151,10 @@ spamm_status spamm_batch_setup(int32_t count, const float* const* a, const float
         q.norm_base = norm_base;
         q.macro_base = macro_base;
         macro_base += q.mb * q.mb;
-        tile_base += g.ntiles;
-        mask_base += g.bdim * g.nwords;
+        if (g.nwords > 1) {
+            tile_base += g.ntiles;
+            mask_base += g.bdim * g.nwords;
+        }
         norm_base += g.bdim * ((g.n + kNormCols - 1) / kNormCols);
     }
     for (int cls = 0; cls < spamm::kBatchClasses; ++cls)
@@ -182,7 +189,8 @@ spamm_status spamm_batch_run(int32_t count, const int64_t* n, const int32_t* lea
     int cus = device_cus();
     cus = (cus + 3) / 4 * 4;  // two groups per CU, a multiple of 8 in all
     return hip_check(spamm::launch_batch(prods, count, members, bp.class_count, class_total, bp.tiles,
-                                         bp.mask_blocks, bp.strips, bp.macros, cus, static_cast<hipStream_t>(stream)),
+                                         bp.mask_blocks, bp.strips, bp.macros, bp.small_count, cus,
+                                         static_cast<hipStream_t>(stream)),
                      "batch kernels");
 }
 

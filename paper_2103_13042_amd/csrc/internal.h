@@ -244,8 +244,8 @@ struct BatchProduct {
     int64_t n, bdim;
     int32_t leaf, lv, nw, vec;
     double tau;
-    int64_t tile_base;  // prefix of bdim^2 over the batch
-    int64_t mask_base;  // prefix of nw * bdim over the batch
+    int64_t tile_base;  // prefix of bdim^2 over the batch's products with nw > 1
+    int64_t mask_base;  // prefix of nw * bdim over the batch's products with nw > 1
     int64_t norm_base;  // prefix of bdim * ceil(n / 1024) (norm-pass strips) over the batch
     int64_t cost_base;  // written on the device: prefix of multiply cost within its leaf class
     // macro-tile schedule (leaf 32 and 64; mb = 0 for leaf 128): k bitmaps,
@@ -263,9 +263,11 @@ constexpr int kBatchClasses = 3;
 
 // members: product indices grouped by class (class_count[c] entries each, in
 // class order); class_total receives each class's total multiply cost.
+// total_tiles and total_mask_blocks count the products with nw > 1 only;
+// small_count is the number of products with nw = 1.
 hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
                         const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
-                        int64_t total_mask_blocks, int64_t total_strips, int64_t total_macros, int num_cus,
-                        hipStream_t s);
+                        int64_t total_mask_blocks, int64_t total_strips, int64_t total_macros, int32_t small_count,
+                        int num_cus, hipStream_t s);
 
 }  // namespace spamm

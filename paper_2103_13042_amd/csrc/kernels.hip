@@ -1061,8 +1061,12 @@ __global__ __launch_bounds__(kNormThreads) void batch_norms_kernel(const BatchPr
     }
 }
 
+// The pyramid, mask, scan and fill launches plan the products with more than
+// 64 tiles per side (the others have no mask blocks and no tiles in the
+// prefixes; the two small-plan launches below plan them).
 __global__ __launch_bounds__(kPyrThreads) void batch_pyramid_kernel(const BatchProduct* __restrict__ P) {
     const BatchProduct& q = P[blockIdx.x];
+    if (q.nw == 1) return;
     pyramid_build(q.spyr[blockIdx.y], q.pyr[blockIdx.y], q.bdim, q.lv);
 }
 
@@ -1079,6 +1083,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_mask_kernel(const Bat
 
 __global__ __launch_bounds__(kScanThreads) void batch_plan_scan_kernel(const BatchProduct* __restrict__ P) {
     const BatchProduct& q = P[blockIdx.x];
+    if (q.nw == 1) return;
     plan_scan_block(q.bsums, q.bdim * q.nw, q.boffs, q.offsets, q.bdim * q.bdim, q.pairs);
 }
 
@@ -1097,6 +1102,99 @@ __global__ __launch_bounds__(256) void batch_plan_fill_kernel(const BatchProduct
             const BatchProduct& q = P[p];
             plan_fill_wave(q.masks, q.counts, q.boffs, q.bdim, q.offsets, q.klist, tg - q.tile_base);
         }
+    }
+}
+
+// Products with at most 64 tiles per side (one k word per tile) are planned
+// by two launches over (product, group of 16 tile rows), in place of the
+// pyramid, mask, scan and fill launches above, which then cover only the
+// larger products.  The node tests there only skip work (a node norm bounds
+// every leaf norm below it, and rounding is monotone), so the kept set is the
+// same.  The test launch: wave w of group g takes tile row i = 16 g + w, B's
+// leaf norms staged in LDS transposed (one tile's k column is a contiguous
+// read), one ballot per tile, and writes the row's bitmaps and its pair count.
+// The fill launch: each row's offset is the sum of the counts of the rows
+// above it; then the row's tiles write their k in ascending order.
+constexpr int kSmallPlanThreads = 1024;
+constexpr int kSmallPlanRows = kSmallPlanThreads / 64;  // tile rows per workgroup
+constexpr int kSmallPlanGroups = 64 / kSmallPlanRows;    // workgroups per product
+constexpr int kSmallPlanPitch = 65;                      // doubles per row of the transposed B norms
+
+__global__ __launch_bounds__(kSmallPlanThreads) void batch_plan_small_test_kernel(const BatchProduct* __restrict__ P) {
+    __shared__ double sbt[64 * kSmallPlanPitch];
+    const BatchProduct& q = P[blockIdx.x];
+    const int bdim = int(q.bdim);
+    if (q.nw != 1 || int(blockIdx.y) * kSmallPlanRows >= bdim) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lv = q.lv, side = 1 << lv;
+    const double tau = q.tau;
+    const double* la = q.pyr[0] + level_offset(lv);
+    const double* lb = q.pyr[1] + level_offset(lv);
+    for (int e = tid; e < side * side; e += kSmallPlanThreads)
+        sbt[(e & (side - 1)) * kSmallPlanPitch + (e >> lv)] = lb[e];
+    __syncthreads();
+    const int i = int(blockIdx.y) * kSmallPlanRows + wave;
+    if (i >= bdim) return;
+    const double a = lane < bdim ? la[i * side + lane] : 0.0;
+    const bool live = lane < bdim;
+    uint64_t mask = 0;
+    for (int j0 = 0; j0 < bdim; j0 += 8) {
+        double bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = sbt[((j0 + u) & 63) * kSmallPlanPitch + lane];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (j0 + u < bdim) {
+                const double p = a * bv[u];
+                const uint64_t m = __ballot(live && p >= tau);
+                if (lane == j0 + u) mask = m;
+            }
+        }
+    }
+    int32_t c = __popcll(mask);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+    if (live) q.masks[i * bdim + lane] = mask;
+    if (lane == 0) q.bsums[i] = c;
+}
+
+__global__ __launch_bounds__(kSmallPlanThreads) void batch_plan_small_fill_kernel(const BatchProduct* __restrict__ P) {
+    const BatchProduct& q = P[blockIdx.x];
+    const int bdim = int(q.bdim);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = int(blockIdx.y) * kSmallPlanRows + wave;
+    if (q.nw != 1 || i >= bdim) return;
+    const int32_t rs = lane < bdim ? q.bsums[lane] : 0;
+    int32_t before = lane < i ? rs : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) before += __shfl_xor(before, o);
+    const bool live = lane < bdim;
+    const uint64_t mask = live ? q.masks[i * bdim + lane] : 0ull;
+    const int32_t c = __popcll(mask);
+    int32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t up = __shfl_up(incl, o);
+        if (lane >= o) incl += up;
+    }
+    const int32_t base = before + incl - c;
+    if (live) q.offsets[i * bdim + lane] = base;
+    if (i == 0) {
+        int32_t total = rs;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o);
+        if (lane == 0) {
+            q.offsets[bdim * bdim] = total;
+            *q.pairs = total;
+        }
+    }
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t mlo = uint32_t(mask), mhi = uint32_t(mask >> 32);
+    for (int j = 0; j < bdim; ++j) {
+        const uint64_t m = uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mlo), j))) |
+                           (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mhi), j))) << 32);
+        const int32_t at = __builtin_amdgcn_readlane(base, j);
+        if ((m >> lane) & 1ull) q.klist[at + __popcll(m & below)] = lane;
     }
 }
 
@@ -1309,17 +1407,24 @@ __global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_batch
 
 hipError_t launch_batch(const BatchProduct* prods, int32_t count, const int32_t* members,
                         const int32_t* class_count_host, int64_t* class_total, int64_t total_tiles,
-                        int64_t total_mask_blocks, int64_t total_strips, int64_t total_macros, int num_cus,
-                        hipStream_t s) {
+                        int64_t total_mask_blocks, int64_t total_strips, int64_t total_macros, int32_t small_count,
+                        int num_cus, hipStream_t s) {
     auto blocks = [](int64_t work, int64_t cap) { return unsigned(work < cap ? (work > 0 ? work : 1) : cap); };
     batch_norms_kernel<<<dim3{blocks(total_strips, 1 << 20), 2u, 1u}, kNormThreads, 0, s>>>(prods, count,
                                                                                            total_strips);
-    batch_pyramid_kernel<<<dim3{unsigned(count), 2u, 1u}, kPyrThreads, 0, s>>>(prods);
-    batch_plan_mask_kernel<<<blocks(total_mask_blocks, 1 << 20), kPlanThreads, 0, s>>>(prods, count,
-                                                                                       total_mask_blocks);
-    batch_plan_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
-    batch_plan_fill_kernel<<<blocks((total_tiles + 4 * kFillRun - 1) / (4 * kFillRun), 1 << 20), 256, 0, s>>>(
-        prods, count, total_tiles);
+    if (total_mask_blocks > 0) {
+        batch_pyramid_kernel<<<dim3{unsigned(count), 2u, 1u}, kPyrThreads, 0, s>>>(prods);
+        batch_plan_mask_kernel<<<blocks(total_mask_blocks, 1 << 20), kPlanThreads, 0, s>>>(prods, count,
+                                                                                           total_mask_blocks);
+        batch_plan_scan_kernel<<<unsigned(count), kScanThreads, 0, s>>>(prods);
+        batch_plan_fill_kernel<<<blocks((total_tiles + 4 * kFillRun - 1) / (4 * kFillRun), 1 << 20), 256, 0, s>>>(
+            prods, count, total_tiles);
+    }
+    if (small_count > 0) {
+        const dim3 grid{unsigned(count), unsigned(kSmallPlanGroups), 1u};
+        batch_plan_small_test_kernel<<<grid, kSmallPlanThreads, 0, s>>>(prods);
+        batch_plan_small_fill_kernel<<<grid, kSmallPlanThreads, 0, s>>>(prods);
+    }
     if (total_macros > 0) {
         const unsigned mblocks = blocks((total_macros + 4 * kMacroRun - 1) / (4 * kMacroRun), 1 << 20);
         batch_macro_words_kernel<<<mblocks, 256, 0, s>>>(prods, count, total_macros);
