@@ -1014,6 +1014,31 @@ hipError_t launch_multiply(const float* a, const float* b, float* c, int64_t n, 
 // block finds its product by binary search over the prefix of its work in the
 // descriptor array, then runs the single-product code on it.
 
+// product i's descriptor with every pointer in it marked as global memory
+__device__ __forceinline__ BatchProduct product_at(const BatchProduct* __restrict__ P, int64_t i) {
+    BatchProduct q = P[i];
+    q.a = global_ptr(q.a);
+    q.b = global_ptr(q.b);
+    q.c = global_ptr(q.c);
+    for (int m = 0; m < 2; ++m) {
+        q.spyr[m] = global_ptr(q.spyr[m]);
+        q.pyr[m] = global_ptr(q.pyr[m]);
+    }
+    q.masks = global_ptr(q.masks);
+    q.counts = global_ptr(q.counts);
+    q.bsums = global_ptr(q.bsums);
+    q.boffs = global_ptr(q.boffs);
+    q.offsets = global_ptr(q.offsets);
+    q.klist = global_ptr(q.klist);
+    q.pair_scratch = global_ptr(q.pair_scratch);
+    q.pairs = global_ptr(q.pairs);
+    q.mwords = global_ptr(q.mwords);
+    q.mcount = global_ptr(q.mcount);
+    q.mprefix = global_ptr(q.mprefix);
+    q.mitems = global_ptr(q.mitems);
+    return q;
+}
+
 constexpr int kFindTile = 0, kFindMask = 1, kFindNorm = 2;
 
 __device__ __forceinline__ int32_t batch_find(const BatchProduct* __restrict__ P, int32_t count, int64_t x,
@@ -1039,19 +1064,21 @@ __device__ __forceinline__ void batch_strip(const BatchProduct& q, int m, int64_
     const int64_t chunks = (q.n + kNormCols - 1) / kNormCols;
     const int64_t side = int64_t(1) << q.lv, at = level_offset(q.lv);
     const float* x = m == 0 ? q.a : q.b;
+    double* sp = (m == 0 ? q.spyr[0] : q.spyr[1]) + at;  // selected, not indexed: q stays in registers
+    double* np = (m == 0 ? q.pyr[0] : q.pyr[1]) + at;
     // chunks fastest here: with the products' strips in strips-fastest order
     // the batch's pass took 1134 against 1086 us
     if (q.vec)
-        leaf_sumsq_strip<LEAF, true>(x, q.n, q.bdim, b / chunks, b % chunks, q.spyr[m] + at, q.pyr[m] + at, side);
+        leaf_sumsq_strip<LEAF, true>(x, q.n, q.bdim, b / chunks, b % chunks, sp, np, side);
     else
-        leaf_sumsq_strip<LEAF, false>(x, q.n, q.bdim, b / chunks, b % chunks, q.spyr[m] + at, q.pyr[m] + at, side);
+        leaf_sumsq_strip<LEAF, false>(x, q.n, q.bdim, b / chunks, b % chunks, sp, np, side);
 }
 
 __global__ __launch_bounds__(kNormThreads) void batch_norms_kernel(const BatchProduct* __restrict__ P, int32_t count,
                                                                    int64_t total_strips) {
     const int m = blockIdx.y;
     for (int64_t bg = blockIdx.x; bg < total_strips; bg += gridDim.x) {
-        const BatchProduct& q = P[batch_find(P, count, bg, kFindNorm)];
+        const BatchProduct q = product_at(P, batch_find(P, count, bg, kFindNorm));
         const int64_t b = bg - q.norm_base;
         switch (q.leaf) {
             case 32: batch_strip<32>(q, m, b); break;
@@ -1065,15 +1092,16 @@ __global__ __launch_bounds__(kNormThreads) void batch_norms_kernel(const BatchPr
 // 64 tiles per side (the others have no mask blocks and no tiles in the
 // prefixes; the two small-plan launches below plan them).
 __global__ __launch_bounds__(kPyrThreads) void batch_pyramid_kernel(const BatchProduct* __restrict__ P) {
-    const BatchProduct& q = P[blockIdx.x];
+    const BatchProduct q = product_at(P, blockIdx.x);
     if (q.nw == 1) return;
-    pyramid_build(q.spyr[blockIdx.y], q.pyr[blockIdx.y], q.bdim, q.lv);
+    const bool b = blockIdx.y != 0;
+    pyramid_build(b ? q.spyr[1] : q.spyr[0], b ? q.pyr[1] : q.pyr[0], q.bdim, q.lv);
 }
 
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_mask_kernel(const BatchProduct* __restrict__ P,
                                                                        int32_t count, int64_t total_blocks) {
     for (int64_t bg = blockIdx.x; bg < total_blocks; bg += gridDim.x) {
-        const BatchProduct& q = P[batch_find(P, count, bg, kFindMask)];
+        const BatchProduct q = product_at(P, batch_find(P, count, bg, kFindMask));
         const int64_t b = bg - q.mask_base;
         plan_mask_block<true, false>(q.pyr[0], q.pyr[1], q.bdim, q.lv, q.tau, q.masks, q.counts, q.bsums, b % q.nw,
                                      b / q.nw);
@@ -1082,7 +1110,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_mask_kernel(const Bat
 }
 
 __global__ __launch_bounds__(kScanThreads) void batch_plan_scan_kernel(const BatchProduct* __restrict__ P) {
-    const BatchProduct& q = P[blockIdx.x];
+    const BatchProduct q = product_at(P, blockIdx.x);
     if (q.nw == 1) return;
     plan_scan_block(q.bsums, q.bdim * q.nw, q.boffs, q.offsets, q.bdim * q.bdim, q.pairs);
 }
@@ -1099,7 +1127,7 @@ __global__ __launch_bounds__(256) void batch_plan_fill_kernel(const BatchProduct
         const int64_t t1 = t0 + kFillRun < total_tiles ? t0 + kFillRun : total_tiles;
         for (int64_t tg = t0; tg < t1; ++tg) {
             while (p + 1 < count && P[p + 1].tile_base <= tg) ++p;
-            const BatchProduct& q = P[p];
+            const BatchProduct q = product_at(P, p);
             plan_fill_wave(q.masks, q.counts, q.boffs, q.bdim, q.offsets, q.klist, tg - q.tile_base);
         }
     }
@@ -1122,7 +1150,7 @@ constexpr int kSmallPlanPitch = 65;                      // doubles per row of t
 
 __global__ __launch_bounds__(kSmallPlanThreads) void batch_plan_small_test_kernel(const BatchProduct* __restrict__ P) {
     __shared__ double sbt[64 * kSmallPlanPitch];
-    const BatchProduct& q = P[blockIdx.x];
+    const BatchProduct q = product_at(P, blockIdx.x);
     const int bdim = int(q.bdim);
     if (q.nw != 1 || int(blockIdx.y) * kSmallPlanRows >= bdim) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1159,7 +1187,7 @@ __global__ __launch_bounds__(kSmallPlanThreads) void batch_plan_small_test_kerne
 }
 
 __global__ __launch_bounds__(kSmallPlanThreads) void batch_plan_small_fill_kernel(const BatchProduct* __restrict__ P) {
-    const BatchProduct& q = P[blockIdx.x];
+    const BatchProduct q = product_at(P, blockIdx.x);
     const int bdim = int(q.bdim);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = int(blockIdx.y) * kSmallPlanRows + wave;
@@ -1227,7 +1255,7 @@ __global__ __launch_bounds__(256) void batch_macro_words_kernel(const BatchProdu
         const int64_t m1 = m0 + kMacroRun < total_macros ? m0 + kMacroRun : total_macros;
         for (int64_t gm = m0; gm < m1; ++gm) {
             while (p + 1 < count && P[p + 1].macro_base <= gm) ++p;
-            const BatchProduct& q = P[p];
+            const BatchProduct q = product_at(P, p);
             macro_words_wave(q.offsets, q.klist, q.bdim, q.mb, q.nw, q.mwords, q.mcount, gm - q.macro_base,
                              sw[wave]);
         }
@@ -1235,7 +1263,7 @@ __global__ __launch_bounds__(256) void batch_macro_words_kernel(const BatchProdu
 }
 
 __global__ __launch_bounds__(kScanThreads) void batch_macro_scan_kernel(const BatchProduct* __restrict__ P) {
-    const BatchProduct& q = P[blockIdx.x];
+    const BatchProduct q = product_at(P, blockIdx.x);
     if (q.mb == 0) return;
     const int64_t nm = q.mb * q.mb;
     plan_scan_block(q.mcount, nm, q.mprefix, q.mprefix, nm, nullptr);
@@ -1250,7 +1278,7 @@ __global__ __launch_bounds__(256) void batch_macro_items_kernel(const BatchProdu
         const int64_t m1 = m0 + kMacroRun < total_macros ? m0 + kMacroRun : total_macros;
         for (int64_t gm = m0; gm < m1; ++gm) {
             while (p + 1 < count && P[p + 1].macro_base <= gm) ++p;
-            const BatchProduct& q = P[p];
+            const BatchProduct q = product_at(P, p);
             macro_items_wave(q.mwords, q.mprefix, q.mb, q.nw, q.mitems, gm - q.macro_base);
         }
     }
@@ -1275,13 +1303,14 @@ __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchProduct* 
         for (int32_t start = 0; start < cnt[c]; start += kCostThreads) {
             const int32_t k = start + tid;
             int64_t cost = 0;
-            BatchProduct* q = k < cnt[c] ? &P[members[first + k]] : nullptr;
-            if (q) {
-                if (q->mb > 0) {
-                    const int64_t nm = q->mb * q->mb;
-                    cost = int64_t(kUnionCost) * q->mprefix[nm] + int64_t(kMacroWrite) * nm;
+            const int32_t idx = k < cnt[c] ? members[first + k] : -1;
+            if (idx >= 0) {
+                const BatchProduct q = product_at(P, idx);
+                if (q.mb > 0) {
+                    const int64_t nm = q.mb * q.mb;
+                    cost = int64_t(kUnionCost) * q.mprefix[nm] + int64_t(kMacroWrite) * nm;
                 } else {
-                    cost = int64_t(kPairCost) * (*q->pairs) + q->bdim * q->bdim;
+                    cost = int64_t(kPairCost) * (*q.pairs) + q.bdim * q.bdim;
                 }
             }
             int64_t incl = cost;
@@ -1294,7 +1323,7 @@ __global__ __launch_bounds__(kCostThreads) void batch_cost_kernel(BatchProduct* 
             __syncthreads();
             int64_t before = carry;
             for (int w = 0; w < wave; ++w) before += wsum[w];
-            if (q) q->cost_base = before + incl - cost;
+            if (idx >= 0) P[idx].cost_base = before + incl - cost;
             int64_t chunk = 0;
             for (int w = 0; w < kCostThreads / 64; ++w) chunk += wsum[w];
             __syncthreads();
@@ -1345,7 +1374,7 @@ __global__ __launch_bounds__(kMacThreads, kBatchMacOcc) void multiply_batch_macr
             hi = mid - 1;
     }
     for (int32_t k = lo; k < nmem; ++k) {
-        const BatchProduct& q = P[members[k]];
+        const BatchProduct q = product_at(P, members[k]);
         if (q.cost_base * groups >= (lg + 1) * total) break;
         const int64_t m0 = batch_macro_partition(q, lg, groups, total);
         const int64_t m1 = batch_macro_partition(q, lg + 1, groups, total);
@@ -1392,7 +1421,7 @@ __global__ __launch_bounds__(kMulThreads, MulCfg<LEAF>::OCC) void multiply_batch
             hi = mid - 1;
     }
     for (int32_t k = lo; k < nmem; ++k) {
-        const BatchProduct& q = P[members[k]];
+        const BatchProduct q = product_at(P, members[k]);
         if (q.cost_base * groups >= (lg + 1) * total) break;
         const int64_t t0 = batch_partition(q, lg, groups, total), t1 = batch_partition(q, lg + 1, groups, total);
         if (t0 >= t1) continue;
