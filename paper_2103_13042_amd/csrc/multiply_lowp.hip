@@ -9,6 +9,189 @@
 namespace spamm {
 
 // ---------------------------------------------------------------------------
+// Work split of the reduced-precision multiplies.  XCD x (the blocks congruent
+// to x mod 8) takes the macro tiles between the cost boundaries x W and
+// (x+1) W of the G-way partition (kUnionCost per union k, kMacroWrite per
+// macro tile; W = G / 8).  Its W workgroups share the range's tiles that have
+// items in snake order of their rank (rank r goes to workgroup r mod W in even
+// rounds, W-1 - (r mod W) in odd ones, as tile costs change slowly along the
+// band), so the workgroups of one XCD work at the same time on neighbouring
+// band tiles, which share A rows and B columns in that XCD's L2; the tiles
+// without items (most of a banded range) are written as zeros by position,
+// workgroup w taking slice w of W.  Without dealing (xcd_deal false) each
+// workgroup takes the contiguous range between its own cost boundaries (the
+// blocks of an XCD neighbouring ranges), the same code with W = 1.  Every
+// macro tile is computed whole by one workgroup in ascending k, so C does not
+// depend on the split.  (Macro tiles number at most 512 x 512 and item
+// positions fit the int32 prefix.)
+constexpr int kDealList = 3072;  // tiles per window of a workgroup's list
+constexpr int kDealBytes = kDealList * 2 * 4 + (kDmaThreads / 64) * 4;
+
+struct Deal {
+    int32_t a, b, W, w;  // the XCD's range [a, b), workgroups per XCD, this one's index
+};
+
+__device__ __forceinline__ Deal deal_of(const int32_t* __restrict__ uprefix, int64_t mb, bool xcd_deal) {
+    const int64_t groups = gridDim.x, bid = blockIdx.x, nm = mb * mb;
+    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
+    auto start_of = [&](int64_t gg) {
+        const int64_t target = gg * total;
+        int64_t lo = 0, hi = nm;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    };
+    Deal d;
+    if (xcd_deal) {
+        d.W = int32_t(groups >> 3);
+        d.w = int32_t(bid >> 3);
+        d.a = int32_t(start_of((bid & 7) * d.W));
+        d.b = int32_t(start_of(((bid & 7) + 1) * d.W));
+    } else {
+        const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
+        d.W = 1;
+        d.w = 0;
+        d.a = int32_t(start_of(lg));
+        d.b = int32_t(start_of(lg + 1));
+    }
+    return d;
+}
+
+// One scan of the XCD's range by the whole block: the item ranges (first,
+// end) of this workgroup's tiles with items of list positions q0 .. q0 +
+// kDealList - 1 go to lst; returns how many such tiles the workgroup has.
+__device__ __forceinline__ int32_t deal_list(const Deal& d, const int32_t* __restrict__ uprefix, int32_t q0,
+                                             int32_t* lst, int32_t* wcount) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int32_t carry = 0;
+    for (int32_t c0 = d.a; c0 < d.b; c0 += kDmaThreads) {
+        const int32_t m = c0 + tid;
+        int32_t lo = 0, hi = 0;
+        if (m < d.b) {
+            lo = uprefix[m];
+            hi = uprefix[m + 1];
+        }
+        const bool has = hi > lo;
+        const uint64_t bal = __ballot(has);
+        if (lane == 0) wcount[wave] = __popcll(bal);
+        __syncthreads();
+        int32_t before = carry, chunk = 0;
+        for (int v = 0; v < kDmaThreads / 64; ++v) {
+            const int32_t c = wcount[v];
+            if (v < wave) before += c;
+            chunk += c;
+        }
+        const int32_t r = before + __popcll(bal & below);
+        const int32_t round = r / d.W, owner = (round & 1) ? d.W - 1 - r % d.W : r % d.W;
+        if (has && owner == d.w) {
+            const int32_t q = round - q0;
+            if (q >= 0 && q < kDealList) {
+                lst[2 * q] = lo;
+                lst[2 * q + 1] = hi;
+            }
+        }
+        carry += chunk;
+        __syncthreads();
+    }
+    const int32_t full = carry / d.W, rem = carry % d.W;
+    return full + (rem > 0 && ((full & 1) ? d.w >= d.W - rem : d.w < rem) ? 1 : 0);
+}
+
+// The workgroup's multiply: for each window of its list, the items of the
+// listed tiles through S LDS stages (copy(item, stage) issues COPIES copies
+// per wave, compute(stage) multiplies the wave's part if its tile keeps the
+// item's k, store(m) writes macro tile m from the accumulators with exactly
+// kDmaStores stores per wave, zero() clears them); then the tiles without
+// items of its slice, written as zeros.  lst and wcount lie in the same LDS
+// object as the stages.
+template <int S, int COPIES, typename Copy, typename Compute, typename Store, typename Zero>
+__device__ __forceinline__ void deal_run(const Deal& d, const uint32_t* __restrict__ items,
+                                         const int32_t* __restrict__ uprefix, int64_t mb, int32_t* lst,
+                                         int32_t* wcount, int tile, Copy copy_item, Compute compute,
+                                         Store store_macro, Zero zero_acc) {
+    const int lane = threadIdx.x & 63;
+    // the items of the listed tiles in turn; past the end the last item
+    // repeats (a harmless reload)
+    int32_t nlist = 0, ci = -1, pp = 0, pend = 0;
+    uint32_t last = 0;
+    auto produce = [&]() -> uint32_t {
+        while (pp >= pend && ci + 1 < nlist) {
+            ++ci;
+            pp = __builtin_amdgcn_readfirstlane(lst[2 * ci]);
+            pend = __builtin_amdgcn_readfirstlane(lst[2 * ci + 1]);
+        }
+        if (pp < pend) last = items[pp++];
+        return last;
+    };
+    zero_acc();
+    const int32_t mine = deal_list(d, uprefix, 0, lst, wcount);
+    for (int32_t q0 = 0; q0 < mine; q0 += kDealList) {
+        if (q0 > 0) deal_list(d, uprefix, q0, lst, wcount);
+        nlist = mine - q0 < kDealList ? mine - q0 : kDealList;
+        ci = -1;
+        pp = pend = 0;
+        int32_t nitems = 0;
+        for (int e = lane; e < nlist; e += 64) nitems += lst[2 * e + 1] - lst[2 * e];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) nitems += __shfl_xor(nitems, o);
+        nitems = __builtin_amdgcn_readfirstlane(nitems);
+        uint32_t f[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) f[i] = produce();
+#pragma unroll
+        for (int i = 0; i < S - 1; ++i) copy_item(f[i], i);
+        int32_t cur_m = -1;  // macro tile being accumulated
+        int ns[S];           // macro tiles stored in the last S-1 steps (ns[0]: this step)
+#pragma unroll
+        for (int i = 0; i < S; ++i) ns[i] = 0;
+        for (int32_t it = 0; it < nitems; ++it) {
+            const uint32_t pi = f[0];
+            const int32_t m_it = int32_t(pi >> 23) * int32_t(mb) + int32_t((pi >> 14) & 511);
+#pragma unroll
+            for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
+            ns[0] = 0;
+            if (m_it != cur_m) {  // listed tiles all have items: one store per change
+                if (cur_m >= 0) {
+                    store_macro(cur_m);
+                    zero_acc();
+                    ++ns[0];
+                }
+                cur_m = m_it;
+            }
+            int stores = 0;
+#pragma unroll
+            for (int i = 0; i < S - 1; ++i) stores += ns[i];
+            asm volatile("" ::: "memory");
+            wait_copies<(S - 2) * COPIES>(stores);
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            copy_item(f[S - 1], int((it + S - 1) % S));  // item it+S-1 -> the stage item it-1 used
+            if ((pi >> tile) & 1) compute(int(it % S));
+#pragma unroll
+            for (int i = 0; i < S - 1; ++i) f[i] = f[i + 1];
+            f[S - 1] = produce();
+        }
+        if (cur_m >= 0) {
+            store_macro(cur_m);
+            zero_acc();
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // the stages are free before the list is rebuilt
+        __syncthreads();
+    }
+    const int32_t len = d.b - d.a;
+    for (int32_t m = d.a + len * d.w / d.W; m < d.a + len * (d.w + 1) / d.W; ++m)
+        if (uprefix[m + 1] == uprefix[m]) store_macro(m);
+    __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
+}
+
+// ---------------------------------------------------------------------------
 // Reduced-precision leaf products (leaf 64, N a multiple of 128): the macro-tile
 // stream of the FP32 DMA kernel (multiply_macro.hip), with operands from the split pass: A rows
 // and Bt rows (columns of B) of 64 halves per leaf k-range, so an item is one
@@ -46,43 +229,19 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
     if (!gate_open(gate)) return;
     using G = LowpGeom<MODE>;
     constexpr int LEAF = 64, S = G::S;
-    __shared__ __attribute__((aligned(1024))) char lds[S * G::STAGE];
+    static_assert(S * G::STAGE + kDealBytes <= 160 * 1024, "LDS budget");
+    __shared__ __attribute__((aligned(1024))) char lds[S * G::STAGE + kDealBytes];  // stages, then the deal's list
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
               qc = (wave >> 2) & 1;
     const int ir = lane & 31, g = lane >> 5;
 
-    const int64_t groups = gridDim.x;
-    const int64_t bid = blockIdx.x;
-    const int64_t lg = (bid & 7) * (groups >> 3) + (bid >> 3);
-    const int64_t nm = mb * mb;
-    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
-    auto start_of = [&](int64_t gg) {
-        const int64_t target = gg * total;
-        int64_t lo = 0, hi = nm;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        return lo;
-    };
-    const int64_t m_begin = start_of(lg), m_end = start_of(lg + 1);
-    if (m_begin >= m_end) return;
-    const int64_t nitems = int64_t(uprefix[m_end] - uprefix[m_begin]);
+    // dealt within each XCD for BF16; FP16 hi+lo (three products per k-step)
+    // measured slower dealt on a dense pair pattern (27.2 -> 32.7 ms at
+    // N = 16384), BF16 faster (16.2 -> 14.5 ms)
+    const Deal d = deal_of(uprefix, mb, MODE == kPrecBf16);
     const float inv = MODE == kPrecF16x3 ? ldexpf(1.0f, -(exps[0] + exps[1])) : 1.0f;
-
-    const uint32_t* ip = items + uprefix[m_begin];
-    int64_t pp = 0;
-    uint32_t last = 0;
-    auto produce = [&]() -> uint32_t {
-        if (pp < nitems) last = ip[pp];
-        ++pp;
-        return last;
-    };
 
     f16v acc;
     auto zero_acc = [&]() {
@@ -156,49 +315,9 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
         }
     };
 
-    uint32_t f[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) f[i] = produce();
-#pragma unroll
-    for (int i = 0; i < S - 1; ++i) copy_item(f[i], i);
-    int64_t out_m = m_begin;
-    int ns[S];  // macro tiles stored in the last S-1 steps (ns[0]: this step)
-#pragma unroll
-    for (int i = 0; i < S; ++i) ns[i] = 0;
-    zero_acc();
-    for (int64_t it = 0; it < nitems; ++it) {
-        const uint32_t pi = f[0];
-        const int64_t m_it = int64_t(pi >> 23) * mb + ((pi >> 14) & 511);
-#pragma unroll
-        for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
-        ns[0] = 0;
-        while (out_m < m_it) {
-            store_macro(out_m);
-            zero_acc();
-            ++out_m;
-            ++ns[0];
-        }
-        int stores = 0;
-#pragma unroll
-        for (int i = 0; i < S - 1; ++i) stores += ns[i];
-        asm volatile("" ::: "memory");
-        wait_copies<(S - 2) * G::COPIES>(stores);
-        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        copy_item(f[S - 1], int((it + S - 1) % S));  // item it+S-1 -> the stage item it-1 used
-        if ((pi >> tile) & 1) compute(int(it % S));
-#pragma unroll
-        for (int i = 0; i < S - 1; ++i) f[i] = f[i + 1];
-        f[S - 1] = produce();
-    }
-    int64_t m_last = out_m;
-    while (m_last < m_end) {
-        store_macro(m_last);
-        zero_acc();
-        ++m_last;
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
+    deal_run<S, G::COPIES>(d, items, uprefix, mb, reinterpret_cast<int32_t*>(lds + S * G::STAGE),
+                           reinterpret_cast<int32_t*>(lds + S * G::STAGE + kDealList * 2 * 4), tile, copy_item,
+                           compute, store_macro, zero_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,104 +344,18 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_fused_kernel(
     constexpr int ABYTES = 2 * LEAF * KC * 4, BBYTES = KC * 2 * LEAF * 4;
     constexpr int STAGE_BYTES = ABYTES + BBYTES;
     constexpr int COPIES = 2 * KC / 32;  // per wave per item
-    // after the stages: a window of this workgroup's macro-tile list (first
-    // item, end of items; the items name their tile) and per-wave counts for
-    // the block scan; one LDS object, as in the FP32 kernel
-    constexpr int LIST = 3072;
-    constexpr int LIST_BYTES = LIST * 2 * 4, WCOUNT_BYTES = 16 * 4;
-    static_assert(S * STAGE_BYTES + LIST_BYTES + WCOUNT_BYTES <= 160 * 1024, "LDS budget");
-    __shared__ __attribute__((aligned(1024))) char lds[S * STAGE_BYTES + LIST_BYTES + WCOUNT_BYTES];
-    int32_t* lst = reinterpret_cast<int32_t*>(lds + S * STAGE_BYTES);
-    int32_t* wcount = reinterpret_cast<int32_t*>(lds + S * STAGE_BYTES + LIST_BYTES);
+    static_assert(S * STAGE_BYTES + kDealBytes <= 160 * 1024, "LDS budget");
+    __shared__ __attribute__((aligned(1024))) char lds[S * STAGE_BYTES + kDealBytes];  // stages, then the deal's list
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
               qc = (wave >> 2) & 1;
     const int ir = lane & 31, g = lane >> 5;
 
-    const int64_t groups = gridDim.x;
-    const int64_t bid = blockIdx.x;
-    const int64_t nm = mb * mb;
-    const int64_t total = int64_t(kUnionCost) * uprefix[nm] + int64_t(kMacroWrite) * nm;
-    auto start_of = [&](int64_t gg) {
-        const int64_t target = gg * total;
-        int64_t lo = 0, hi = nm;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if ((int64_t(kUnionCost) * uprefix[mid] + int64_t(kMacroWrite) * mid) * groups >= target)
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        return lo;
-    };
-    // XCD x (blocks congruent mod 8) takes the macro tiles between cost
-    // boundaries x W and (x+1) W of the G-way partition.  Its W workgroups
-    // deal the range's tiles that have items round-robin by rank (workgroup w:
-    // ranks w, w + W, ...), so the workgroups of one XCD work at the same time
-    // on neighbouring tiles of the band, which share A rows and B columns in
-    // that XCD's L2; the tiles without items (most of the range, off the band)
-    // are written as zeros by position, workgroup w taking slice w of W.
-    // (macro tiles number at most 512 x 512, item positions fit the int32 prefix)
-    const int32_t xcd = int32_t(bid & 7), W = int32_t(groups >> 3), w = int32_t(bid >> 3);
-    const int32_t a_x = int32_t(start_of(int64_t(xcd) * W)), b_x = int32_t(start_of(int64_t(xcd + 1) * W));
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // list this workgroup's tiles with items of ranks [w + W q0, w + W (q0 +
-    // LIST)) into lst (one scan of the range by the whole block); returns how
-    // many of this workgroup's tiles the range holds in all
-    auto build_list = [&](int32_t q0) -> int32_t {
-        int32_t carry = 0;
-        for (int32_t c0 = a_x; c0 < b_x; c0 += kDmaThreads) {
-            const int32_t m = c0 + tid;
-            int32_t lo = 0, hi = 0;
-            if (m < b_x) {
-                lo = uprefix[m];
-                hi = uprefix[m + 1];
-            }
-            const bool has = hi > lo;
-            const uint64_t bal = __ballot(has);
-            if (lane == 0) wcount[wave] = __popcll(bal);
-            __syncthreads();
-            int32_t before = carry, chunk = 0;
-            for (int v = 0; v < kDmaThreads / 64; ++v) {
-                const int32_t c = wcount[v];
-                if (v < wave) before += c;
-                chunk += c;
-            }
-            const int32_t r = before + __popcll(bal & below);
-            // rank r goes to workgroup r mod W in even rounds, W-1 - (r mod W)
-            // in odd ones (costs change slowly along the band)
-            const int32_t round = r / W, owner = (round & 1) ? W - 1 - r % W : r % W;
-            if (has && owner == w) {
-                const int32_t q = round - q0;
-                if (q >= 0 && q < LIST) {
-                    lst[2 * q] = lo;
-                    lst[2 * q + 1] = hi;
-                }
-            }
-            carry += chunk;
-            __syncthreads();
-        }
-        const int32_t full = carry / W, rem = carry % W;
-        return full + (rem > 0 && ((full & 1) ? w >= W - rem : w < rem) ? 1 : 0);
-    };
+    const Deal d = deal_of(uprefix, mb, true);
     constexpr bool F16 = MODE == kPrecF16x3;  // else BF16: no scales (exps may be null)
     const float sa_scale = F16 ? ldexpf(1.0f, exps[0]) : 1.0f, sb_scale = F16 ? ldexpf(1.0f, exps[1]) : 1.0f;
     const float inv = F16 ? ldexpf(1.0f, -(exps[0] + exps[1])) : 1.0f;
-
-    // the items of the listed tiles in turn; past the end the last item
-    // repeats (a harmless reload)
-    int32_t nlist = 0, ci = -1, pp = 0, pend = 0;
-    uint32_t last = 0;
-    auto produce = [&]() -> uint32_t {
-        while (pp >= pend && ci + 1 < nlist) {
-            ++ci;
-            pp = __builtin_amdgcn_readfirstlane(lst[2 * ci]);
-            pend = __builtin_amdgcn_readfirstlane(lst[2 * ci + 1]);
-        }
-        if (pp < pend) last = items[pp++];
-        return last;
-    };
 
     f16v acc;
     auto zero_acc = [&]() {
@@ -412,67 +445,9 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_fused_kernel(
         }
     };
 
-    zero_acc();
-    const int32_t mine = build_list(0);
-    for (int32_t q0 = 0; q0 < mine; q0 += LIST) {
-        if (q0 > 0) build_list(q0);
-        nlist = mine - q0 < LIST ? mine - q0 : LIST;
-        ci = -1;
-        pp = pend = 0;
-        int32_t nitems = 0;
-        for (int e = lane; e < nlist; e += 64) nitems += lst[2 * e + 1] - lst[2 * e];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) nitems += __shfl_xor(nitems, o);
-        nitems = __builtin_amdgcn_readfirstlane(nitems);
-        uint32_t f[S];
-#pragma unroll
-        for (int i = 0; i < S; ++i) f[i] = produce();
-#pragma unroll
-        for (int i = 0; i < S - 1; ++i) copy_item(f[i], i);
-        int32_t cur_m = -1;  // macro tile being accumulated
-        int ns[S];           // macro tiles stored in the last S-1 steps (ns[0]: this step)
-#pragma unroll
-        for (int i = 0; i < S; ++i) ns[i] = 0;
-        for (int32_t it = 0; it < nitems; ++it) {
-            const uint32_t pi = f[0];
-            const int32_t m_it = int32_t(pi >> 23) * int32_t(mb) + int32_t((pi >> 14) & 511);
-#pragma unroll
-            for (int i = S - 1; i > 0; --i) ns[i] = ns[i - 1];
-            ns[0] = 0;
-            if (m_it != cur_m) {  // listed tiles all have items: one store per change
-                if (cur_m >= 0) {
-                    store_macro(cur_m);
-                    zero_acc();
-                    ++ns[0];
-                }
-                cur_m = m_it;
-            }
-            int stores = 0;
-#pragma unroll
-            for (int i = 0; i < S - 1; ++i) stores += ns[i];
-            asm volatile("" ::: "memory");
-            wait_copies<(S - 2) * COPIES>(stores);
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
-            copy_item(f[S - 1], int((it + S - 1) % S));  // item it+S-1 -> the stage item it-1 used
-            if ((pi >> tile) & 1) compute(int(it % S));
-#pragma unroll
-            for (int i = 0; i < S - 1; ++i) f[i] = f[i + 1];
-            f[S - 1] = produce();
-        }
-        if (cur_m >= 0) {
-            store_macro(cur_m);
-            zero_acc();
-        }
-        __builtin_amdgcn_s_waitcnt(0);  // the stages are free before the list is rebuilt
-        __syncthreads();
-    }
-    // tiles without items in this workgroup's slice of the range: zeros
-    const int32_t len = b_x - a_x;
-    for (int32_t m = a_x + len * w / W; m < a_x + len * (w + 1) / W; ++m)
-        if (uprefix[m + 1] == uprefix[m]) store_macro(m);
-    __builtin_amdgcn_s_waitcnt(0);  // no copy into LDS may outlive the workgroup
+    deal_run<S, COPIES>(d, items, uprefix, mb, reinterpret_cast<int32_t*>(lds + S * STAGE_BYTES),
+                        reinterpret_cast<int32_t*>(lds + S * STAGE_BYTES + kDealList * 2 * 4), tile, copy_item,
+                        compute, store_macro, zero_acc);
 }
 
 hipError_t launch_fused_multiply(const float* a, const float* b, int precision, const int32_t* exps, float* c,
