@@ -106,10 +106,23 @@ def test_multiply_precision_matches_oracle(precision, n, kind, tau):
     assert _check(c.cpu().numpy(), a, b, tau, 64, precision) == pairs
 
 
+def _signed_with_zeros_and_tiny(n, seed):
+    # signed entries, negative zeros and entries scaled down by 2^-20 (their
+    # FP16 lo parts are subnormal or zero), to pin the in-register rounding
+    x = inputs.algebraic_decay_signed(n, seed)
+    x[::7, ::5] = -0.0
+    x[1::9, ::3] *= np.float32(2.0**-20)
+    return x
+
+
+@pytest.mark.parametrize("kind", ["exp", "signed"])
 @pytest.mark.parametrize("precision", ["bf16", "f16x3"])
-def test_staged_split_path_equals_fused(precision):
+def test_staged_split_path_equals_fused(precision, kind):
     n, leaf, tau = 1024, 64, 1e-6
-    a, b = inputs.exp_decay(n, 0.02, 5), inputs.exp_decay(n, 0.02, 6)
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.02, 5), inputs.exp_decay(n, 0.02, 6)
+    else:
+        a, b = _signed_with_zeros_and_tiny(n, 5), _signed_with_zeros_and_tiny(n, 6)
     ga, gb = gpu(a), gpu(b)
     c_fused, _ = sp.multiply_precision(ga, gb, tau, leaf, precision)
     ws = sp.workspace(n, leaf, DEV)
