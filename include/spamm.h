@@ -161,9 +161,9 @@ spamm_status spamm_prepare(const float* a, const float* b, int64_t n, double tau
  * plan and the multiply schedule come from one launch (the norm tests,
  * bitmaps, map_offset and validNum of Algorithm 2 and the union k-lists of
  * section 3.5.1's work split, with the prefix over tile rows by a
- * single-pass look-back) instead of six; with at most 128 tiles per side that
- * launch tests every k-chunk on the leaf norms, and the pyramid above the
- * leaf level is not built.  Errors as spamm_prepare and spamm_schedule. */
+ * single-pass look-back) instead of six; that launch (up to 256 tiles per
+ * side) tests every triple on the leaf norms, and the pyramid above the leaf
+ * level is not built.  Errors as spamm_prepare and spamm_schedule. */
 spamm_status spamm_prepare_schedule(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
                                     int32_t* offsets, int32_t* klist, int64_t klist_capacity, int64_t* pairs,
                                     void* workspace, size_t workspace_bytes, void* stream);

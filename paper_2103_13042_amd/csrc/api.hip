@@ -242,11 +242,10 @@ spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, doub
     const float* xs[2] = {a, b};
     double* ps[2] = {pa, pb};
     const bool fused = schedule && (g.leaf == 32 || g.leaf == 64) && g.bdim <= spamm::kPlanMacroMaxBdim;
-    // the fused plan needs the pyramid above the leaves only for its node tests
-    const bool node_tests = g.bdim >= spamm::kPlanMacroNodeTestMinBdim;
+    // the fused plan tests on the leaf norms alone: no pyramid levels above
     int64_t* state = at<int64_t>(ws, L.pm_state);
     spamm_status st = enqueue_pyramids(g, xs, 2, ps, ws, s, fused ? state : nullptr,
-                                       fused ? spamm::plan_macro_clear_words(g.bdim) : 0, !fused || node_tests);
+                                       fused ? spamm::plan_macro_clear_words(g.bdim) : 0, !fused);
     if (st != SPAMM_OK) return st;
     if (!fused) {
         if ((st = enqueue_plan(g, pa, pb, tau, false, offsets, klist, pairs, ws, s)) != SPAMM_OK) return st;
@@ -261,7 +260,8 @@ spamm_status enqueue_prepare(const Geom& g, const float* a, const float* b, doub
     o.items = ms.items;
     o.flags = reinterpret_cast<unsigned long long*>(state);
     o.ticket = reinterpret_cast<unsigned int*>(state + (g.bdim + 1) / 2);
-    return hip_check(spamm::launch_plan_macro(pa, pb, g.bdim, g.lv, tau, node_tests, o, s),
+    const int64_t leaf_level = spamm::level_offset(g.lv);
+    return hip_check(spamm::launch_plan_macro(pa + leaf_level, pb + leaf_level, g.side, g.bdim, tau, o, s),
                      "plan and schedule kernel");
 }
 

@@ -73,13 +73,10 @@ struct PlanMacroOut {
     unsigned int* ticket;
 };
 inline int64_t plan_macro_clear_words(int64_t bdim) { return (bdim + 1) / 2 + 1; }
-// Up to this many tiles per side the plan opens every k-chunk (at most four)
-// without the pyramid's node tests, so the pyramid above the leaf level is
-// not needed and not built; the kept pairs come from the leaf tests either way.
-constexpr int64_t kPlanMacroNodeTestMinBdim = 129;
-// node_tests: settle k-chunks on the pyramid's level lv-6 nodes (or its root)
-hipError_t launch_plan_macro(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
-                             bool node_tests, const PlanMacroOut& o, hipStream_t s);
+// norms_a, norms_b: the leaf norms (row stride side); the pyramid above the
+// leaf level is not used
+hipError_t launch_plan_macro(const double* norms_a, const double* norms_b, int64_t side, int64_t bdim, double tau,
+                             const PlanMacroOut& o, hipStream_t s);
 
 // Small products (leaf 32, bdim <= kSmallMaxBdim, n % 4 == 0, a and b 16-byte
 // aligned): the threshold test on the leaf norms na / nb (row stride ld) and

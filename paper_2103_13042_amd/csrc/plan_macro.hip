@@ -1,20 +1,20 @@
 // The pruning plan and the macro-tile schedule of the multiply in one launch
 // (leaf 32 and 64): the work of plan_mask, plan_scan, plan_fill (the bitmap,
-// map_offset and validNum of Algorithm 2, and Algorithm 1's norm tests with
-// whole k-ranges settled on a pyramid node as in the plan kernel) and of
+// map_offset and validNum of Algorithm 2, and Algorithm 1's norm tests) and of
 // macro_words, its scan and macro_items (the union k-lists of 2x2 blocks of
 // output tiles that the multiply streams, section 3.5.1's balanced work
-// split reads their prefix), with identical outputs.
+// split reads their prefix), with identical outputs.  Every triple is tested
+// on the leaf norms: the plan kernel's node tests on the pyramid only skip
+// work (a node norm bounds every leaf norm below it, and rounding is
+// monotone), and at these grid sizes building the pyramid for them cost more
+// than they saved, so the pyramid above the leaf level is not needed here.
 //
 // One workgroup of sixteen waves per macro-tile row I (output tile rows 2I
 // and 2I+1), taken in order of a ticket so that every lower row's workgroup
 // has started; grids of up to 256 tiles per side, so that the row pair's
 // bitmaps stay in LDS:
-//  1. the tests: per k-chunk of 64 (with more than 128 tiles per side, one
-//     pyramid node of 64 x 64 leaf tiles on each side settles the chunk for 64
-//     tile columns when its product is below tau; with at most four chunks
-//     every chunk is tested, the pyramid above the leaves then not built),
-//     B's leaf norms staged in LDS, one ballot per (tile, chunk)
+//  1. the tests: per (64-column block, k-chunk of 64), B's leaf norms staged
+//     in LDS, one ballot per (tile, chunk)
 //     gives the bitmap of kept k (kept in LDS); per tile the count V, per
 //     macro tile the size of the union of its four bitmaps;
 //  2. the row's two sums (kept pairs, union entries) are combined with those
@@ -69,10 +69,10 @@ __device__ __forceinline__ void lds_barrier() {
 }
 }  // namespace
 
-__global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __restrict__ pyr_a,
-                                                                const double* __restrict__ pyr_b, int64_t bdim,
-                                                                int lv, double tau, int node_tests,
-                                                                PlanMacroOut o) {
+// la, lb: leaf norms of A and B, row stride `side`
+__global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __restrict__ la,
+                                                                const double* __restrict__ lb, int64_t side,
+                                                                int64_t bdim, double tau, PlanMacroOut o) {
     __shared__ double sb[64][65];                         // B leaf norms of a chunk: [k][j]
     __shared__ uint64_t smask[2][kPmMaxBdim][kPmMaxNw];   // bitmaps of the row pair's tiles
     __shared__ int32_t tcount[2][kPmMaxBdim];             // V of the row pair's tiles
@@ -80,49 +80,19 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
     __shared__ int64_t wsum[2][kPmWaves];
     __shared__ unsigned long long s_excl;
     __shared__ int64_t s_row;
-    __shared__ uint32_t s_settled;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_row = atomicAdd(o.ticket, 1u);
-    const int64_t side = int64_t(1) << lv;
     const int64_t mb = (bdim + 1) / 2, nm = mb * mb;
     const int nw = int((bdim + 63) / 64);
-    const double* la = pyr_a + level_offset(lv);
-    const double* lb = pyr_b + level_offset(lv);
     __syncthreads();
     const int64_t I = s_row;
     if (I >= mb) return;       // only if the ticket was not cleared before the launch
     const int64_t r0 = 2 * I;  // tile rows r0 and r0 + 1 (the latter may lie outside the grid)
 
-    // ---- 1. tests, bitmaps, counts
-    // The node tests of every (column block jb, k-chunk c) first, one lane
-    // each (bit jb * nw + c of `settled`: no triple of that chunk is kept for
-    // any tile of the block); then the chunks that remain, the norms of the
-    // next one loaded while this one is tested.
-    if (wave == 0) {
-        bool below = false;
-        if (node_tests && lane < nw * nw) {
-            const int jb = lane / nw, c = lane - (lane / nw) * nw;
-            if (lv >= 6) {
-                const int lc = lv - 6;
-                const int64_t w = int64_t(1) << lc;
-                below = !(pyr_a[level_offset(lc) + (r0 >> 6) * w + c] * pyr_b[level_offset(lc) + int64_t(c) * w + jb] >=
-                          tau);
-            } else {
-                below = !(pyr_a[0] * pyr_b[0] >= tau);
-            }
-        }
-        const uint64_t bits = __ballot(below);
-        if (lane == 0) s_settled = uint32_t(bits);
-    }
-    __syncthreads();
-    const uint32_t settled = s_settled;
+    // ---- 1. tests, bitmaps, counts: every (column block jb, k-chunk c), the
+    // norms of the next one loaded while this one is tested
     const int nit = nw * nw;
-    auto next_open = [&](int from) {
-        int it = from;
-        while (it < nit && ((settled >> it) & 1u)) ++it;
-        return it;
-    };
     // this thread's four entries of a chunk's B norms, and the A norms of
     // rows r0 and r0 + 1 at lane's k
     double vb[4], va[2];
@@ -138,8 +108,7 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
         va[0] = k < side ? la[r0 * side + k] : 0.0;
         va[1] = (k < side && r0 + 1 < side) ? la[(r0 + 1) * side + k] : 0.0;
     };
-    int open = next_open(0);
-    if (open < nit) fetch(open);
+    fetch(0);
     for (int64_t jb = 0; jb < nw; ++jb) {
         // wave w: macro columns J = 32 jb + w + 16 u (u = 0, 1) of this column block
         int cnt[2][4], uc[2];
@@ -151,14 +120,6 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
         }
         for (int c = 0; c < nw; ++c) {
             const int it = int(jb) * nw + c;
-            if ((settled >> it) & 1u) {  // no triple of the chunk is kept, for any tile of the block
-                if (tid < 128) {
-                    const int h = tid >> 6;
-                    const int64_t j = jb * 64 + (tid & 63);
-                    if (j < bdim) smask[h][j][c] = 0ull;
-                }
-                continue;
-            }
             const double a0 = va[0], a1 = va[1];
             lds_barrier();  // every wave is done with the previous chunk's norms
 #pragma unroll
@@ -167,8 +128,7 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
                 sb[e >> 6][e & 63] = vb[u];
             }
             lds_barrier();
-            open = next_open(it + 1);
-            if (open < nit) fetch(open);  // in flight during this chunk's tests
+            if (it + 1 < nit) fetch(it + 1);  // in flight during this chunk's tests
             const int64_t k = int64_t(c) * 64 + lane;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -342,11 +302,11 @@ __global__ __launch_bounds__(kPmThreads) void plan_macro_kernel(const double* __
     }
 }
 
-hipError_t launch_plan_macro(const double* pyr_a, const double* pyr_b, int64_t bdim, int lv, double tau,
-                             bool node_tests, const PlanMacroOut& o, hipStream_t s) {
-    if (bdim < 1 || bdim > kPmMaxBdim) return hipErrorInvalidValue;
+hipError_t launch_plan_macro(const double* norms_a, const double* norms_b, int64_t side, int64_t bdim, double tau,
+                             const PlanMacroOut& o, hipStream_t s) {
+    if (bdim < 1 || bdim > kPmMaxBdim || side < bdim) return hipErrorInvalidValue;
     const int64_t mb = (bdim + 1) / 2;
-    plan_macro_kernel<<<unsigned(mb), kPmThreads, 0, s>>>(pyr_a, pyr_b, bdim, lv, tau, node_tests ? 1 : 0, o);
+    plan_macro_kernel<<<unsigned(mb), kPmThreads, 0, s>>>(norms_a, norms_b, side, bdim, tau, o);
     return hipGetLastError();
 }
 
