@@ -116,7 +116,9 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     __shared__ __attribute__((aligned(1024))) char lds[kDmaStages * STAGE_BYTES + 6 * sizeof(int64_t)];
     int64_t(*sbound)[2] = reinterpret_cast<int64_t(*)[2]>(lds + kDmaStages * STAGE_BYTES);
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave index as a scalar, so that what derives from it (the tile, the
+    // copy half and its membership tests) stays in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // waves w, w+4, w+8, w+12 share a SIMD: give them different output tiles
     // (and each tile one wave per quadrant), so every SIMD holds one wave of
     // each tile and the MFMA work of an item is spread evenly whichever tiles
@@ -213,30 +215,45 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
     auto aswz = [](int r) { return KC == 32 ? ((r >> 1) & 7) : (r & 15); };
     const int half = wave >> 3;
     const uint32_t need_a = half ? 12u : 3u, need_b = half ? 10u : 5u;
+    // each copy's address: the item's part (uniform: a scalar base) plus the
+    // lane's part, the same for every item (a 32-bit byte offset computed
+    // once: row r of the copy's block times n, plus its swizzled chunk), so
+    // the copies of an item cost no per-lane address arithmetic
+    uint32_t a_off[KC / 32], b_off[KC / 32];
+#pragma unroll
+    for (int j = 0; j < KC / 32; ++j) {
+        {  // A: 1024 / (4 KC) rows per instruction
+            const int blk = wave * (KC / 32) + j;
+            const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
+            a_off[j] = uint32_t((int64_t(r) * n + 4 * (p ^ aswz(r))) * 4);
+        }
+        {  // B: 4 rows of 16 chunks of one half per instruction
+            const int blk = (wave & 7) * (KC / 32) + j;
+            const int r = blk * 4 + (lane >> 4), p = lane & 15;
+            b_off[j] = uint32_t((int64_t(r) * n + half * LEAF + 4 * (p ^ (8 * ((r / SPC) & 1)))) * 4);
+        }
+    }
     auto copy_item = [&](uint32_t pi, int ch, int st) {
         const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
         char* sbase = lds + st * STAGE_BYTES;
         if (pi & need_a) {
+            const char* base = reinterpret_cast<const char*>(A + 2 * I * LEAF * n + kt * LEAF + ch * KC);
 #pragma unroll
-            for (int j = 0; j < KC / 32; ++j) {  // A: 1024 / (4 KC) rows per instruction
+            for (int j = 0; j < KC / 32; ++j) {
                 const int blk = wave * (KC / 32) + j;
-                const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
-                const int c = p ^ aswz(r);
-                const float* src = A + (2 * I * LEAF + r) * n + kt * LEAF + ch * KC + 4 * c;
-                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sbase + blk * 1024),
-                                                 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(base + a_off[j]),
+                                                 (__attribute__((address_space(3))) void*)(sbase + blk * 1024), 16, 0,
+                                                 0);
             }
         }
         if (pi & need_b) {
+            const char* base = reinterpret_cast<const char*>(B + (kt * LEAF + ch * KC) * n + 2 * J * LEAF);
 #pragma unroll
-            for (int j = 0; j < KC / 32; ++j) {  // B: 4 rows of 16 chunks of one half per instruction
+            for (int j = 0; j < KC / 32; ++j) {
                 const int blk = (wave & 7) * (KC / 32) + j;
-                const int r = blk * 4 + (lane >> 4), p = lane & 15;
-                const int c = p ^ (8 * ((r / SPC) & 1));
-                const float* src = B + (kt * LEAF + ch * KC + r) * n + 2 * J * LEAF + half * LEAF + 4 * c;
                 __builtin_amdgcn_global_load_lds(
-                    src, (__attribute__((address_space(3))) void*)(sbase + ABYTES + half * BHALF + blk * 1024), 16, 0,
-                    0);
+                    reinterpret_cast<const float*>(base + b_off[j]),
+                    (__attribute__((address_space(3))) void*)(sbase + ABYTES + half * BHALF + blk * 1024), 16, 0, 0);
             }
         }
     };
