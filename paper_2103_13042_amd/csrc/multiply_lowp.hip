@@ -215,6 +215,10 @@ struct LowpGeom {
     static_assert(S * STAGE <= 160 * 1024, "LDS budget");
 };
 
+// the wave's index in its workgroup as a scalar, so that what derives from
+// it (its tile and copy rows) stays in scalar registers
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6); }
+
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
     static_assert(S * G::STAGE + kDealBytes <= 160 * 1024, "LDS budget");
     __shared__ __attribute__((aligned(1024))) char lds[S * G::STAGE + kDealBytes];  // stages, then the deal's list
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_index();
     const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
               qc = (wave >> 2) & 1;
     const int ir = lane & 31, g = lane >> 5;
@@ -255,21 +259,30 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_lowp_kernel(
         for (int r = 0; r < 16; ++r) dst[(8 * (r >> 2) + (r & 3)) * n] = acc[r] * inv;
     };
     // one 1 KiB copy per plane per wave: rows wave*8 .. wave*8+7 of the stage
+    // the lane's part of each copy's address (row rr of its block, swizzled
+    // chunk) is the same for every item: a byte offset computed once; the
+    // item's part is a scalar base
+    const int lrow = wave * 8 + (lane >> 3), lchunk = (lane & 7) ^ (lrow & 7);
+    const uint32_t lane_off = uint32_t((int64_t(lrow) * n + 8 * lchunk) * 2);
     auto copy_item = [&](uint32_t pi, int st) {
         const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
-        const int rr = wave * 8 + (lane >> 3), c = (lane & 7) ^ (rr & 7);
         char* sbase = lds + st * G::STAGE + wave * 1024;
-        const int64_t aoff = (2 * I * LEAF + rr) * n + kt * LEAF + 8 * c;
-        const int64_t boff = (2 * J * LEAF + rr) * n + kt * LEAF + 8 * c;
-        __builtin_amdgcn_global_load_lds(Ah + aoff, (__attribute__((address_space(3))) void*)(sbase), 16, 0, 0);
-        if (G::NP == 2)
-            __builtin_amdgcn_global_load_lds(Al + aoff, (__attribute__((address_space(3))) void*)(sbase + G::PLANE),
-                                             16, 0, 0);
-        __builtin_amdgcn_global_load_lds(Bh + boff,
-                                         (__attribute__((address_space(3))) void*)(sbase + G::NP * G::PLANE), 16, 0, 0);
-        if (G::NP == 2)
-            __builtin_amdgcn_global_load_lds(
-                Bl + boff, (__attribute__((address_space(3))) void*)(sbase + 3 * G::PLANE), 16, 0, 0);
+        const int64_t aoff = 2 * I * LEAF * n + kt * LEAF, boff = 2 * J * LEAF * n + kt * LEAF;  // item's part
+        const uint16_t* ah = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(Ah + aoff) + lane_off);
+        const uint16_t* bh = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(Bh + boff) + lane_off);
+        __builtin_amdgcn_global_load_lds(ah, (__attribute__((address_space(3))) void*)(sbase), 16, 0, 0);
+        if (G::NP == 2) {
+            const uint16_t* al = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(Al + aoff) + lane_off);
+            __builtin_amdgcn_global_load_lds(al, (__attribute__((address_space(3))) void*)(sbase + G::PLANE), 16, 0,
+                                             0);
+        }
+        __builtin_amdgcn_global_load_lds(bh, (__attribute__((address_space(3))) void*)(sbase + G::NP * G::PLANE), 16,
+                                         0, 0);
+        if (G::NP == 2) {
+            const uint16_t* bl = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(Bl + boff) + lane_off);
+            __builtin_amdgcn_global_load_lds(bl, (__attribute__((address_space(3))) void*)(sbase + 3 * G::PLANE), 16,
+                                             0, 0);
+        }
     };
     auto compute = [&](int st) {
         const char* sa = lds + st * G::STAGE;
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_fused_kernel(
     static_assert(S * STAGE_BYTES + kDealBytes <= 160 * 1024, "LDS budget");
     __shared__ __attribute__((aligned(1024))) char lds[S * STAGE_BYTES + kDealBytes];  // stages, then the deal's list
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_index();
     const int tile = (wave + (wave >> 2)) & 3, wa = tile >> 1, wb = tile & 1, qr = (wave >> 3) & 1,
               qc = (wave >> 2) & 1;
     const int ir = lane & 31, g = lane >> 5;
@@ -370,25 +383,37 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_fused_kernel(
     };
     // copies of item pi into stage st: 2 A and 2 B instructions of 1 KiB per wave
     constexpr int ACH = KC / 4;  // 16-byte chunks per A row
+    // the lane's part of each copy's address (row of its block and swizzled
+    // chunk) is the same for every item: byte offsets computed once; the
+    // item's part is a scalar base
+    uint32_t a_off[KC / 32], b_off[KC / 32];
+#pragma unroll
+    for (int j = 0; j < KC / 32; ++j) {
+        const int blk = wave * (KC / 32) + j;
+        {  // A: 4 rows of 16 chunks per instruction
+            const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
+            a_off[j] = uint32_t((int64_t(r) * n + 4 * (p ^ (r & 15))) * 4);
+        }
+        {  // B: 2 rows of 32 chunks per instruction
+            const int r = blk * 2 + (lane >> 5), p = lane & 31;
+            b_off[j] = uint32_t((int64_t(r) * n + 4 * (p ^ (8 * ((r >> 5) & 1)))) * 4);
+        }
+    }
     auto copy_item = [&](uint32_t pi, int st) {
         const int64_t I = pi >> 23, J = (pi >> 14) & 511, kt = (pi >> 4) & 1023;
         char* sbase = lds + st * STAGE_BYTES;
+        const char* abase = reinterpret_cast<const char*>(A + 2 * I * LEAF * n + kt * LEAF);
+        const char* bbase = reinterpret_cast<const char*>(B + kt * LEAF * n + 2 * J * LEAF);
 #pragma unroll
-        for (int j = 0; j < KC / 32; ++j) {  // A: 4 rows of 16 chunks per instruction
+        for (int j = 0; j < KC / 32; ++j) {
             const int blk = wave * (KC / 32) + j;
-            const int r = blk * (256 / KC) + lane / ACH, p = lane % ACH;
-            const int c = p ^ (r & 15);
-            const float* src = A + (2 * I * LEAF + r) * n + kt * LEAF + 4 * c;
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(sbase + blk * 1024), 16, 0,
-                                             0);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(abase + a_off[j]),
+                                             (__attribute__((address_space(3))) void*)(sbase + blk * 1024), 16, 0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < KC / 32; ++j) {  // B: 2 rows of 32 chunks per instruction
+        for (int j = 0; j < KC / 32; ++j) {
             const int blk = wave * (KC / 32) + j;
-            const int r = blk * 2 + (lane >> 5), p = lane & 31;
-            const int c = p ^ (8 * ((r >> 5) & 1));
-            const float* src = B + (kt * LEAF + r) * n + 2 * J * LEAF + 4 * c;
-            __builtin_amdgcn_global_load_lds(src,
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(bbase + b_off[j]),
                                              (__attribute__((address_space(3))) void*)(sbase + ABYTES + blk * 1024),
                                              16, 0, 0);
         }
