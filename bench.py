@@ -9,8 +9,10 @@ spamm_prepare_schedule (leaf norms and pyramids of A and B, then the plan for
 tau and the multiply schedule from one launch), then spamm_execute_scheduled
 (the MFMA multiply kernel of the kept pairs).  (Reduced precision: the staged
 calls spamm_prepare*, spamm_schedule, the multiply.)  HIP events on the stream
-the library launches on bracket every step and each stage inside it; the
-roofline figure uses the multiply kernel's own time.
+the library launches on bracket K steps run back to back (the step time),
+then K more steps with an event around each stage (the stage times; the
+roofline figure uses the multiply launch's own time from these).  The other
+thresholds of the sweep are timed before the headline threshold's warm-up.
 
   --write-traffic FETCH_CSV WRITE_CSV  turns two rocprofv3 --pmc runs of this
   script into profiles/multiply_traffic.json (HBM bytes per multiply launch).
@@ -326,9 +328,19 @@ def main() -> int:
             end.record()
             torch.cuda.synchronize()
             ms = start.elapsed_time(end) / steps
-            return ms, [0.0, 0.0, ms], int(bufs[2].item())
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+            return ms, [0.0, 0.0, ms], int(bufs[2].item()), ms
+        # the step time: K steps back to back with no event between their
+        # launches (an event record in the stream costs a few microseconds)
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(steps):
+            step(t)
+        end.record()
+        torch.cuda.synchronize()
+        plain = start.elapsed_time(end) / steps
+        # then K more with events around each stage: the stage times and the
+        # multiply launch's duration for the roofline
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         start.record()
         for e in ev:
             e[0].record()
@@ -341,10 +353,10 @@ def main() -> int:
             e[3].record()
         end.record()
         torch.cuda.synchronize()
-        total = start.elapsed_time(end)
+        instrumented = start.elapsed_time(end) / steps
         stages = [float(np.mean([e[q].elapsed_time(e[q + 1]) for e in ev])) for q in range(3)]
         pairs = int(bufs[2].item())
-        return total / steps, stages, pairs
+        return plain, stages, pairs, instrumented
 
     kname, ksrc = multiply_kernel(n, leaf, prec, staged)
     if one_call:
@@ -352,12 +364,47 @@ def main() -> int:
         kname = ("spamm_multiply: leaf norms + multiply_small_kernel" if small else "spamm_multiply (all launches)")
         ksrc = None
     workload = workload_name(n, leaf, tau, args.workload, args.alpha, prec)
-    log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
-    ms_step, (prep_ms, sched_ms, kern_ms), pairs = timed(tau, args.steps, args.warmup)
-    dense_equiv = 2.0 * n**3 / (ms_step * 1e-3) / 1e12
-    # MFMA flops the multiply kernel executes: the three FP16 products triple them
-    flops_mul = 2.0 * leaf**3 * pairs * (3 if prec == "f16x3" else 1)
+    # The dense FP32 GEMM the speedup is quoted against.
+    d = None
+    if not args.no_dense:
+        for _ in range(2):
+            d = torch.matmul(a, b)
+        torch.cuda.synchronize()
+        reps = 5
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(reps):
+            d = torch.matmul(a, b)
+        s1.record()
+        torch.cuda.synchronize()
+        dense_ms = s0.elapsed_time(s1) / reps
+    # MFMA flops the multiply kernel executes per kept pair: the three FP16
+    # products triple them
+    flops_pair = 2.0 * leaf**3 * (3 if prec == "f16x3" else 1)
     peak = PEAK_FP32_MFMA_TFLOPS if prec == "fp32" else PEAK_F16_MFMA_TFLOPS
+
+    # The other thresholds first, briefly.  From an idle GPU the multiply
+    # kernel's first few dozen launches run up to ~25 % slower than later
+    # ones while the chip's power management settles (it also slows the
+    # dense GEMM's first launches); running these points first lets the
+    # headline's steps run at the clock the chip sustains.
+    sweep = {}
+    for tok in [s for s in args.sweep.split(",") if s.strip()]:
+        t = float(tok)
+        ms, (_, _, em), p, _ = timed(t, max(5, args.steps // 2), 2)
+        sweep[f"{t:g}"] = {
+            "ms_per_step": round(ms, 4),
+            "dense_equiv_tflops": round(2.0 * n**3 / (ms * 1e-3) / 1e12, 3),
+            "multiply_ms": round(em, 4),
+            "mfma_frac": round(flops_pair * p / (em * 1e-3) / 1e12 / peak, 4) if p else None,
+            "pairs": p,
+        }
+        log(f"tau={t:g}: {ms:.3f} ms/step, pairs {p}")
+
+    log(f"warmup {args.warmup}, timing {args.steps} steps at tau={tau:g}")
+    ms_step, (prep_ms, sched_ms, kern_ms), pairs, ms_instr = timed(tau, args.steps, args.warmup)
+    dense_equiv = 2.0 * n**3 / (ms_step * 1e-3) / 1e12
+    flops_mul = flops_pair * pairs
     achieved = flops_mul / (kern_ms * 1e-3) / 1e12
     log(f"{ms_step:.3f} ms/step (prepare {prep_ms:.3f}, schedule {sched_ms:.3f}, {kname} {kern_ms:.3f}), "
         f"pairs {pairs}, {dense_equiv:.1f} dense-equiv TFLOP/s, multiply {achieved:.1f} TFLOP/s")
@@ -388,6 +435,8 @@ def main() -> int:
     }
     if fused_plan:  # spamm_prepare_schedule: the schedule comes with the plan
         result["stages_ms"] = {"prepare_schedule": round(prep_ms, 4), "multiply": round(kern_ms, 4)}
+    # the step time of the event-instrumented pass the stages come from
+    result["stages_ms"]["step_with_stage_events"] = round(ms_instr, 4)
     if one_call:
         result["stages_ms"] = {"spamm_multiply": round(ms_step, 4)}
         result["config"]["entry"] = "spamm_multiply"
@@ -407,19 +456,9 @@ def main() -> int:
     if one_call:
         result["roofline"]["note"] = "ms_per_launch is the whole call (every launch of spamm_multiply)"
 
-    # approximation + precision against the dense FP32 product
-    if not args.no_dense:
-        for _ in range(2):
-            d = torch.matmul(a, b)
-        torch.cuda.synchronize()
-        reps = 5
-        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s0.record()
-        for _ in range(reps):
-            d = torch.matmul(a, b)
-        s1.record()
-        torch.cuda.synchronize()
-        dense_ms = s0.elapsed_time(s1) / reps
+    # approximation + precision against the dense FP32 product (which was
+    # timed before the steps)
+    if d is not None:
         rel = float(torch.linalg.norm(c.double() - d.double()) / torch.linalg.norm(d.double()))
         result["dense_gemm"] = {
             "library": f"torch.matmul fp32 (torch {torch.__version__}, TF32 off)",
@@ -431,22 +470,8 @@ def main() -> int:
         log(f"dense {dense_ms:.3f} ms, speedup {dense_ms / ms_step:.2f}x, rel err vs dense {rel:.2e}")
         del d
 
-    sweep = {}
-    for tok in [s for s in args.sweep.split(",") if s.strip()]:
-        t = float(tok)
-        ms, (_, _, em), p = timed(t, max(5, args.steps // 2), 2)
-        sweep[f"{t:g}"] = {
-            "ms_per_step": round(ms, 4),
-            "dense_equiv_tflops": round(2.0 * n**3 / (ms * 1e-3) / 1e12, 3),
-            "multiply_ms": round(em, 4),
-            "mfma_frac": round(flops_mul / pairs * p / (em * 1e-3) / 1e12 / peak, 4) if pairs else None,
-            "pairs": p,
-        }
-        log(f"tau={t:g}: {ms:.3f} ms/step, pairs {p}")
     if sweep:
         result["tau_sweep"] = sweep
-        step(tau)  # leave C of the headline tau for the comparison below
-        torch.cuda.synchronize()
 
     if not args.no_cpu_baseline:
         if a_np is None:
