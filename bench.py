@@ -5,10 +5,12 @@ Default workload: algebraic-decay matrices A_ij = s_ij / (1 + |i-j|)^2 with
 random signs (A seed 0, B seed 1), N = 8192, FP32, leaf tiles of 64, tau = 1e-6.
 
 One step = one pass of the whole hot path over the resident inputs:
-spamm_prepare_schedule (leaf norms and pyramids of A and B, then the plan for
-tau and the multiply schedule from one launch), then spamm_execute_scheduled
-(the MFMA multiply kernel of the kept pairs).  (Reduced precision: the staged
-calls spamm_prepare*, spamm_schedule, the multiply.)  HIP events on the stream
+spamm_prepare_schedule (leaf norms of A and B, then the plan for tau and the
+multiply schedule from one launch), then spamm_execute_scheduled (the MFMA
+multiply kernel of the kept pairs).  (Reduced precision: the same first stage,
+with the FP16 hi+lo scale exponents, spamm_prepare_schedule_scales, then the
+in-register multiply; with the split planes spamm_prepare_split,
+spamm_schedule, the planes' multiply.)  HIP events on the stream
 the library launches on bracket K steps run back to back (the step time),
 then K more steps with an event around each stage (the stage times; the
 roofline figure uses the multiply launch's own time from these).  The other
@@ -272,9 +274,9 @@ def main() -> int:
     # the first stage also
     # writes the split operands (spamm_prepare_split) and the multiply reads
     # them; below that the multiply converts the FP32 tiles in registers
-    # (BF16: spamm_prepare, spamm_execute_bf16_scheduled; FP16 hi+lo: the first
-    # stage adds the scale exponents, spamm_prepare_scales, then
-    # spamm_execute_f16x3_scheduled).
+    # (BF16: spamm_prepare_schedule, spamm_execute_bf16_scheduled; FP16 hi+lo:
+    # the first stage adds the scale exponents, spamm_prepare_schedule_scales,
+    # then spamm_execute_f16x3_scheduled), as spamm_multiply_precision runs it.
     staged = False
     if prec != "fp32":
         sp.prepare(a, b, tau, leaf, bufs=bufs, ws=ws)
@@ -282,17 +284,16 @@ def main() -> int:
         if staged:
             split_buf = sp.split_buffer(n, prec, dev)
 
-    # FP32: the first stage is spamm_prepare_schedule (norms, pyramids, then
-    # the plan and the multiply schedule from one launch), so no schedule stage
-    fused_plan = prec == "fp32"
+    # FP32 and the in-register forms: the first stage is spamm_prepare_schedule
+    # (norms, then the plan and the multiply schedule from one launch; FP16
+    # hi+lo adds the scale exponents), so no schedule stage
+    fused_plan = prec == "fp32" or not staged
 
     def stage_prepare(t):
+        if prec == "f16x3" and not staged:
+            return sp.prepare_scales(a, b, t, leaf, header, bufs=bufs, ws=ws, schedule=True)
         if fused_plan:
             return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws, schedule=True)
-        if prec == "bf16" and not staged:
-            return sp.prepare(a, b, t, leaf, bufs=bufs, ws=ws)
-        if prec == "f16x3" and not staged:
-            return sp.prepare_scales(a, b, t, leaf, header, bufs=bufs, ws=ws)
         return sp.prepare_split(a, b, t, leaf, prec, split_buf, bufs=bufs, ws=ws)
 
     def stage_multiply(offsets, klist):

@@ -263,6 +263,20 @@ spamm_status spamm_prepare_scales(const float* a, const float* b, int64_t n, dou
                                   void* header, size_t header_bytes, void* workspace, size_t workspace_bytes,
                                   void* stream);
 
+/* spamm_prepare_schedule followed by spamm_split_scales on the leaf norms it
+ * leaves in the workspace: the plan, the multiply schedule and the FP16 hi+lo
+ * scale exponents, so that spamm_execute_f16x3_scheduled can follow directly
+ * (the first stage of the in-register F16X3 path of spamm_multiply_precision,
+ * which uses the one-launch plan and schedule where spamm_prepare_schedule
+ * does).  Arguments as spamm_prepare_scales; the same offsets, k-lists, pairs
+ * and header.  The header (256-byte aligned, at least 256 bytes, not
+ * overlapping a or b: else EINVAL or ENOSPACE) is checked before anything is
+ * enqueued.  Other errors as spamm_prepare_schedule. */
+spamm_status spamm_prepare_schedule_scales(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                           int32_t* offsets, int32_t* klist, int64_t klist_capacity,
+                                           int64_t* pairs, void* header, size_t header_bytes, void* workspace,
+                                           size_t workspace_bytes, void* stream);
+
 /* spamm_prepare followed by spamm_split on the pyramids it leaves in the
  * workspace (the first half of spamm_multiply_precision).  Errors as
  * spamm_prepare and spamm_split. */
@@ -272,14 +286,14 @@ spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, doub
                                  size_t workspace_bytes, void* stream);
 
 /* The whole path with reduced-precision products.  F16X3:
- * spamm_prepare_scales into the first 256 bytes of `split`, spamm_schedule,
- * then either the planes and the split multiply (spamm_split's planes,
+ * spamm_prepare_schedule_scales into the first 256 bytes of `split`, then
+ * either the planes and the split multiply (spamm_split's planes,
  * spamm_execute_split_scheduled) or the in-register split
  * (spamm_execute_f16x3_scheduled), picked on the device from the plan's pair
  * count: the planes when it keeps at least 25 pairs per output tile on
  * average.  With split_bytes below spamm_split_bytes (at least 256), always
  * in registers and the planes are not written.  BF16: the same with
- * spamm_prepare (no scales) and spamm_execute_bf16_scheduled, the planes from
+ * spamm_prepare_schedule (no scales) and spamm_execute_bf16_scheduled, the planes from
  * 16 pairs per tile; split may be NULL (then always in registers).  Either
  * way C is bitwise the C of the split path.  SPAMM_PREC_FP32 is
  * spamm_multiply (split unused, may be NULL).  Errors as spamm_multiply and

@@ -60,6 +60,8 @@ _SIGS = {
     "spamm_execute_split_scheduled": (_st, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_split_scales": (_st, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
     "spamm_prepare_scales": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
+    "spamm_prepare_schedule_scales": (_st, [_vp, _vp, _i64, _f64, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz,
+                                            _vp]),
     "spamm_execute_f16x3_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_execute_bf16_scheduled": (_st, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spamm_prepare_split": (_st, [_vp, _vp, _i64, _f64, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp, _sz, _vp]),
@@ -531,17 +533,21 @@ def split_scales(pyr_a, pyr_b, n: int, leaf: int, header=None) -> torch.Tensor:
     return header
 
 
-def prepare_scales(a, b, tau: float, leaf: int, header, *, bufs=None, ws=None):
-    """spamm_prepare + spamm_split_scales on the workspace pyramids: (offsets, klist, pairs)."""
+def prepare_scales(a, b, tau: float, leaf: int, header, *, bufs=None, ws=None, schedule: bool = False):
+    """spamm_prepare + spamm_split_scales on the workspace pyramids (with
+    schedule=True spamm_prepare_schedule_scales: also the multiply schedule,
+    from the one-launch plan): (offsets, klist, pairs)."""
     n = _square_f32(a, "a")
     if _square_f32(b, "b") != n:
         raise ValueError("a and b must have the same size")
     dev = a.device
     ws = workspace(n, leaf, dev) if ws is None else ws
     offsets, klist, pairs = plan_buffers(n, leaf, dev) if bufs is None else bufs
-    _check(_lib.spamm_prepare_scales(_ptr(a), _ptr(b), n, float(tau), leaf, _ptr(offsets), _ptr(klist), klist.numel(),
-                                     _ptr(pairs), _ptr(header), header.numel(), _ptr(ws), ws.numel(), _stream(dev)),
-           "spamm_prepare_scales")
+    fn, name = ((_lib.spamm_prepare_schedule_scales, "spamm_prepare_schedule_scales") if schedule
+                else (_lib.spamm_prepare_scales, "spamm_prepare_scales"))
+    _check(fn(_ptr(a), _ptr(b), n, float(tau), leaf, _ptr(offsets), _ptr(klist), klist.numel(), _ptr(pairs),
+              _ptr(header), header.numel(), _ptr(ws), ws.numel(), _stream(dev)),
+           name)
     return offsets, klist, pairs
 
 

@@ -705,6 +705,32 @@ spamm_status spamm_prepare_scales(const float* a, const float* b, int64_t n, dou
                               header_bytes, stream);
 }
 
+spamm_status spamm_prepare_schedule_scales(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
+                                           int32_t* offsets, int32_t* klist, int64_t klist_capacity,
+                                           int64_t* pairs, void* header, size_t header_bytes, void* workspace,
+                                           size_t workspace_bytes, void* stream) {
+    g_last_error[0] = '\0';
+    Geom g;
+    if (!make_geom(n, leaf, &g)) return fail(SPAMM_EINVAL, "bad size n=%lld leaf=%d", (long long)n, leaf);
+    spamm_status st = check_lowp(g, spamm::kPrecF16x3);
+    if (st != SPAMM_OK) return st;
+    // the header is checked before anything is enqueued
+    if (!header || (reinterpret_cast<uintptr_t>(header) & 255u) != 0)
+        return fail(SPAMM_EINVAL, "the header must be non-null and 256-byte aligned");
+    if (header_bytes < kSplitHeaderBytes)
+        return fail(SPAMM_ENOSPACE, "header of %zu bytes, %zu needed", header_bytes, kSplitHeaderBytes);
+    const size_t mbytes = sizeof(float) * size_t(n) * size_t(n);
+    if (overlaps(header, kSplitHeaderBytes, a, mbytes) || overlaps(header, kSplitHeaderBytes, b, mbytes))
+        return fail(SPAMM_EINVAL, "header overlaps a or b");
+    st = spamm_prepare_schedule(a, b, n, tau, leaf, offsets, klist, klist_capacity, pairs, workspace,
+                                workspace_bytes, stream);
+    if (st != SPAMM_OK) return st;
+    // the scale kernels read the leaf level, which either form of the plan leaves
+    const Layout L = make_layout(g);
+    return spamm_split_scales(at<double>(workspace, L.pyr[0]), at<double>(workspace, L.pyr[1]), n, leaf, header,
+                              header_bytes, stream);
+}
+
 spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, double tau, int32_t leaf,
                                  int32_t precision, int32_t* offsets, int32_t* klist, int64_t klist_capacity,
                                  int64_t* pairs, void* split, size_t split_bytes, void* workspace,

@@ -144,6 +144,39 @@ def test_staged_split_path_equals_fused(precision, kind):
         assert torch.equal(sp.execute_bf16(ga, gb, leaf, offsets, klist, ws=ws), c1)
 
 
+@pytest.mark.parametrize("n,kind", [(1024, "exp"), (1024, "signed"), (640, "exp")])
+def test_prepare_schedule_scales_equals_the_staged_calls(n, kind):
+    """spamm_prepare_schedule_scales (one-launch plan and schedule, then the
+    scale exponents) gives the offsets, k-lists, pairs and header of
+    spamm_prepare_scales + spamm_schedule, and the in-register FP16 hi+lo
+    multiply after it gives bitwise the same C."""
+    leaf, tau = 64, 1e-6
+    if kind == "exp":
+        a, b = inputs.exp_decay(n, 0.02, 11), inputs.exp_decay(n, 0.02, 12)
+    else:
+        a, b = _signed_with_zeros_and_tiny(n, 11), _signed_with_zeros_and_tiny(n, 12)
+    ga, gb = gpu(a), gpu(b)
+    ws1, ws2 = sp.workspace(n, leaf, DEV), sp.workspace(n, leaf, DEV)
+    h1 = torch.zeros(256, dtype=torch.uint8, device=DEV)
+    h2 = torch.full((256,), 7, dtype=torch.uint8, device=DEV)
+    o1, k1, p1 = sp.prepare_scales(ga, gb, tau, leaf, h1, ws=ws1)
+    sp.schedule(o1, k1, n, leaf, ws=ws1)
+    o2, k2, p2 = sp.prepare_scales(ga, gb, tau, leaf, h2, ws=ws2, schedule=True)
+    pairs = int(p1.item())
+    assert pairs == int(p2.item()) and pairs > 0
+    assert torch.equal(o1, o2) and torch.equal(k1[:pairs], k2[:pairs])
+    assert torch.equal(h1[:8], h2[:8])
+    c1 = sp.execute_f16x3(ga, gb, leaf, h1, o1, k1, ws=ws1)
+    c2 = sp.execute_f16x3(ga, gb, leaf, h2, o2, k2, ws=ws2)
+    assert torch.equal(c1, c2)
+    ea, eb = (pr.f16_scale_exponent(pr.max_leaf_norm(x, leaf)) for x in (a, b))
+    assert h2[:8].view(torch.int32).cpu().tolist() == [ea, eb]
+    # the header is checked before anything is enqueued
+    with pytest.raises(sp.SpammError) as e:
+        sp.prepare_scales(ga, gb, tau, leaf, torch.zeros(255, dtype=torch.uint8, device=DEV), ws=ws2, schedule=True)
+    assert e.value.status == 2
+
+
 def test_f16x3_whole_path_needs_only_the_split_header():
     n, leaf, tau = 512, 64, 1e-6
     a, b = gpu(inputs.exp_decay(n, 0.05, 7)), gpu(inputs.exp_decay(n, 0.05, 8))
