@@ -438,9 +438,14 @@ def main() -> int:
         result["stages_ms"] = {"prepare_schedule": round(prep_ms, 4), "multiply": round(kern_ms, 4)}
     # the step time of the event-instrumented pass the stages come from
     result["stages_ms"]["step_with_stage_events"] = round(ms_instr, 4)
+    result["timing"] = (f"after the tau sweep: {args.warmup} warm-up steps, {args.steps} steps back to back "
+                        f"(ms_per_step), then {args.steps} steps with an event around each stage (stages_ms, "
+                        "roofline.ms_per_launch)")
     if one_call:
         result["stages_ms"] = {"spamm_multiply": round(ms_step, 4)}
         result["config"]["entry"] = "spamm_multiply"
+        result["timing"] = (f"after the tau sweep: {args.warmup} warm-up calls, {args.steps} calls back to back "
+                            "(ms_per_step and roofline.ms_per_launch)")
 
     tr = traffic_entry(kname, ksrc, workload) if ksrc else None
     result["roofline"] = {
