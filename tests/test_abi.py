@@ -106,6 +106,28 @@ def test_plan_capacity_check(lib):
     assert st == 1
 
 
+def test_prepare_schedule_scales_checks_the_header_first(lib):
+    # every case fails host-side validation before anything is enqueued, so
+    # the fake pointers are never used
+    from paper_2103_13042_amd import binding as bd
+
+    vp = ctypes.c_void_p
+    n, leaf = 1024, 64
+    cap, wsb = bd.bdim(n, leaf) ** 3, bd.workspace_bytes(n, leaf)
+
+    def call(header, header_bytes=256, n=n, leaf=leaf, a=_FAKE_A):
+        return lib.spamm_prepare_schedule_scales(vp(a), vp(_FAKE_B), n, 1e-6, leaf, vp(3 << 28), vp(4 << 28), cap,
+                                                 vp(5 << 28), vp(header), header_bytes, vp(_FAKE_WS), wsb, None)
+
+    assert call(0) == 1  # null header
+    assert call((6 << 28) + 16) == 1  # not 256-byte aligned
+    assert call(6 << 28, header_bytes=255) == 2  # too small
+    assert call(_FAKE_A + 4096) == 1  # inside A (4 MiB at n = 1024)
+    assert b"overlaps" in lib.spamm_last_error()
+    assert call(6 << 28, leaf=32) == 4  # FP16 hi+lo products need leaf 64
+    assert call(6 << 28, n=1000) == 4  # and n a multiple of 128
+
+
 def test_binding_rejects_cpu_tensors():
     import torch
 
