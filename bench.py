@@ -47,7 +47,7 @@ CALIB_BYTES = 256 << 20  # device copy whose counter readings scale the HBM byte
 
 # the library's choice between the two forms of reduced-precision products:
 # split planes from this many kept pairs per output tile, else in registers
-LOWP_STAGED_PAIRS_PER_TILE = {"bf16": 16, "f16x3": 25}
+LOWP_STAGED_PAIRS_PER_TILE = {"bf16": 16, "f16x3": 45}
 
 
 def multiply_kernel(n: int, leaf: int, precision: str = "fp32", staged: bool = False) -> tuple[str, list[Path]]:
@@ -106,6 +106,9 @@ def parse_args():
     ap.add_argument("--alpha", type=float, default=0.05, help="decay rate of --workload exp")
     ap.add_argument("--precision", choices=["fp32", "bf16", "f16x3"], default="fp32",
                     help="leaf-product precision (the mask is always the FP32 inputs')")
+    ap.add_argument("--form", choices=["auto", "planes", "registers"], default="auto",
+                    help="reduced precision: split planes or in-register conversion (auto: as the library picks, "
+                         "from the plan's pairs per output tile)")
     ap.add_argument("--one-call", action="store_true",
                     help="time spamm_multiply as one call (fp32; leaf 32 with at most 64 tiles per side takes the "
                          "two-launch small-product path)")
@@ -270,7 +273,7 @@ def main() -> int:
     # bracket the multiply kernel alone.
     # Reduced-precision products, as spamm_multiply_precision picks on the
     # device (decided here once, from the pair count of a first pass): with at
-    # least 16 (BF16) or 25 (FP16 hi+lo) kept pairs per output tile on average
+    # least 16 (BF16) or 45 (FP16 hi+lo) kept pairs per output tile on average
     # the first stage also
     # writes the split operands (spamm_prepare_split) and the multiply reads
     # them; below that the multiply converts the FP32 tiles in registers
@@ -281,6 +284,8 @@ def main() -> int:
     if prec != "fp32":
         sp.prepare(a, b, tau, leaf, bufs=bufs, ws=ws)
         staged = int(bufs[2].item()) >= LOWP_STAGED_PAIRS_PER_TILE[prec] * (n // leaf) ** 2
+        if args.form != "auto":
+            staged = args.form == "planes"
         if staged:
             split_buf = sp.split_buffer(n, prec, dev)
 
@@ -429,6 +434,7 @@ def main() -> int:
             "leaf": leaf,
             "tau": tau,
             "precision": prec,
+            "form": ("fp32" if prec == "fp32" else "split planes" if staged else "in registers"),
             "pairs": pairs,
             "valid_ratio": pairs / bd**3,
         },

@@ -290,7 +290,7 @@ spamm_status spamm_prepare_split(const float* a, const float* b, int64_t n, doub
  * either the planes and the split multiply (spamm_split's planes,
  * spamm_execute_split_scheduled) or the in-register split
  * (spamm_execute_f16x3_scheduled), picked on the device from the plan's pair
- * count: the planes when it keeps at least 25 pairs per output tile on
+ * count: the planes when it keeps at least 45 pairs per output tile on
  * average.  With split_bytes below spamm_split_bytes (at least 256), always
  * in registers and the planes are not written.  BF16: the same with
  * spamm_prepare_schedule (no scales) and spamm_execute_bf16_scheduled, the planes from

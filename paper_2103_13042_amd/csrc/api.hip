@@ -328,16 +328,16 @@ spamm_status enqueue_execute(const Geom& g, const float* a, const float* b, cons
 namespace {
 constexpr size_t kSplitHeaderBytes = 256;  // scale exponents and largest leaf norms
 // F16X3 whole path: split A and B once when the plan keeps at least this many
-// pairs per output tile on average, else split in registers.  The in-register
-// split costs about 0.6 ns per kept pair more in the multiply (measured on the
-// dense N = 16384 ReLU-like pair, where it is VALU-bound), the split pass
-// about 15 ns per output tile (it reads and writes A and B: 1 ms at
-// N = 16384, 65,536 tiles), so they break even near 25 pairs per tile.
-constexpr int64_t kF16x3StagedPairsPerTile = 25;
-// BF16: the in-register rounding costs 0.5-1.3 ns per kept pair more in the
-// multiply (the FP32 tiles are twice the bytes of the planes), the split pass
-// 11 ns per output tile (measured at N = 16384: break-even at 8 pairs per tile
-// on exponential decay, 22 on the dense ReLU-like pair).
+// pairs per output tile on average, else split in registers.  The split pass
+// reads and writes A and B once more (1 ms at N = 16384); the in-register
+// split redoes the conversions in every wave that reads an operand, work that
+// grows with the kept pairs.  Whole steps measured at N = 16384 on
+// exponential decay cross near 50 pairs per tile (in registers 5.84 against
+// 6.26 ms at 30 pairs per tile, planes 13.40 against 13.74 ms at 74).
+constexpr int64_t kF16x3StagedPairsPerTile = 45;
+// BF16: the in-register rounding reads the FP32 tiles (twice the bytes of the
+// planes); the same measurement crosses near 19 pairs per tile (in registers
+// 1.46 against 1.91 ms at 8 pairs per tile, planes 3.30 against 3.77 ms at 30).
 constexpr int64_t kBf16StagedPairsPerTile = 16;
 size_t plane_bytes(int64_t n) { return (size_t(n) * size_t(n) * 2 + 255) / 256 * 256; }
 int split_planes(int32_t precision) { return precision == spamm::kPrecF16x3 ? 4 : 2; }
