@@ -489,12 +489,15 @@ def alg8192():
     return inputs.workload_alg8192()
 
 
-@pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 64)])
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (1000, 64), (1024, 64), (2048, 128)])
 def test_one_call_graph_replays_equal_eager_run(n, leaf):
-    """spamm_multiply captured in a graph (the small-product path at leaf 32,
-    the general path at leaf 64) and replayed three times with eager work in
-    between: every replay equals the eager call bitwise, C and pairs (the pair
-    counter is cleared by a kernel, not a memset)."""
+    """spamm_multiply captured in a graph (the small-product path at leaf 32;
+    at leaf 64 the register-staged multiply for n = 1000 and, for n a
+    multiple of 128, the one-launch plan with its look-back state and the
+    LDS-DMA multiply with its fixup kernel; the leaf-128 DMA path) and
+    replayed three times with eager work in between: every replay equals the
+    eager call bitwise, C and pairs (the pair counter and the plan's state are
+    cleared by a kernel, not a memset)."""
     a, b = inputs.exp_decay(n, 0.02, 28), inputs.exp_decay(n, 0.02, 29)
     ga, gb = gpu(a), gpu(b)
     ws = sp.workspace(n, leaf, DEV)
