@@ -211,6 +211,39 @@ def test_whole_path_picks_either_form_with_the_same_result(precision, tau):
     assert (p_adapt >= {"f16x3": 45, "bf16": 16}[precision] * (n // leaf) ** 2) == (tau == 0.0)
 
 
+@pytest.mark.parametrize("precision", ["f16x3", "bf16"])
+@pytest.mark.parametrize("tau", [0.0, 1e-6])
+def test_whole_path_graph_replays_equal_eager_run(precision, tau):
+    """spamm_multiply_precision captured in a graph and replayed three times
+    with eager work in between: the form is picked on the device from the
+    plan's pair count (tau = 0: the planes; 1e-6: in registers), so every
+    replay equals the eager call bitwise, C and pairs."""
+    n, leaf = 3072, 64
+    a, b = gpu(inputs.exp_decay(n, 0.02, 41)), gpu(inputs.exp_decay(n, 0.02, 42))
+    ws = sp.workspace(n, leaf, DEV)
+    split_buf = sp.split_buffer(n, precision, DEV)
+    c = torch.empty((n, n), device=DEV)
+    pairs = torch.empty(1, dtype=torch.int64, device=DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        sp.multiply_precision(a, b, tau, leaf, precision, c=c, pairs=pairs, split_buf=split_buf, ws=ws, sync=False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    eager_c, eager_pairs = c.clone(), pairs.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sp.multiply_precision(a, b, tau, leaf, precision, c=c, pairs=pairs, split_buf=split_buf, ws=ws, sync=False)
+    for r in range(3):
+        c.fill_(7.0)
+        pairs.fill_(-5)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(c, eager_c), r
+        assert torch.equal(pairs, eager_pairs), r
+
+
 def test_zero_and_tau_above_every_product():
     n = 512
     z = torch.zeros(n, n, device=DEV)
