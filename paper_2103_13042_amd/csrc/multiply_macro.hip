@@ -281,6 +281,10 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
                 bv[buf][u] = *reinterpret_cast<const float*>(brow + kr * (LEAF * 4));
             }
         };
+        // a wave in its MFMA block goes first in its SIMD's issue arbitration,
+        // ahead of the waves that issue their copies or wait at the barrier,
+        // so the matrix unit is not left idle while copies are issued
+        __builtin_amdgcn_s_setprio(1);
         load(0, 0);
 #pragma unroll
         for (int grp = 0; grp < NGRP; ++grp) {
@@ -290,6 +294,7 @@ __global__ __launch_bounds__(kDmaThreads, 1) void multiply_macro_dma_kernel(
             for (int u = 0; u < GRP; ++u)
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[grp & 1][u >> 2][u & 3], bv[grp & 1][u], acc, 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
     };
 
     // pair items of item it (f[0]) and of the next pairs; item it + S - 1 lies
